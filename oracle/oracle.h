@@ -1,0 +1,114 @@
+/*
+ * oracle.h -- plain FP64 CPU reference of the sensor-prior featuremetric
+ * Levenberg-Marquardt pose solver (PiLoT v2, arXiv 2606.31098).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library; the product path never
+ * does.  It shares no code, header or constant with the GPU library.
+ *
+ * Conventions (each reading of the paper is listed in the design notes):
+ *   pose      world->camera, double[12] = R row-major (9), t (3);
+ *             X_cam = R X + t.
+ *   update    T <- Exp(xi) * T with xi = (rho; omega), translation first.
+ *   pixels    integer coordinates are pixel centres; a point is visible iff
+ *             Z > z_min and 0 <= u <= W-1 and 0 <= v <= H-1.
+ *   features  channels-last H x W x C; reference descriptors N x C.
+ *   DSM       Hd x Wd heights; sample (i, j) sits at (x0 + j*gsd, y0 + i*gsd);
+ *             bilinear with clamp-to-edge.
+ */
+#ifndef PILOT_ORACLE_H
+#define PILOT_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_CAUCHY = 0, ORC_HUBER = 1, ORC_L2 = 2 };
+enum { ORC_CONVERGED = 0, ORC_MAX_ITERS = 1, ORC_STALLED = 2, ORC_DEGENERATE = 3 };
+
+typedef struct {
+    int H, W, C;
+    const double *feat;      /* H*W*C */
+    const double *qconf;     /* H*W or NULL (query confidence, treated as constant in J) */
+    double fx, fy, cx, cy;
+    int N;
+    const double *P;         /* N*3 world points */
+    const double *ref;       /* N*C reference descriptors */
+    const double *ref_w;     /* N or NULL */
+    int iters;
+    int loss_kind;
+    double loss_scale;
+} orc_level;
+
+typedef struct {
+    int n_levels;
+    orc_level lv[4];
+    int use_gravity;
+    double g_imu[3], g_world[3], lambda_imu;
+    int grav_loss_kind;
+    double grav_loss_scale;
+    int use_range;
+    double d_range, pc[2], lambda_range;
+    int range_loss_kind;
+    double range_loss_scale;
+    const double *dsm;
+    int Hd, Wd;
+    double dsm_x0, dsm_y0, dsm_gsd;
+    double tau, up, down, lam_min_rel, lam_max_rel, tol_t, tol_r, z_min;
+    int min_valid;
+} orc_frame;
+
+/* SE(3) */
+void orc_exp(const double xi[6], double T[12]);
+void orc_log(const double T[12], double xi[6]);
+void orc_compose(const double A[12], const double B[12], double AB[12]);
+
+/* robust loss rho(s) and its derivative rho'(s) */
+void orc_robust(int kind, double b, double s, double *rho, double *drho);
+
+/* bilinear value and derivatives d/du, d/dv of a channels-last map (C values
+ * each); requires 0 <= u <= W-1, 0 <= v <= H-1, H, W >= 2 */
+void orc_bilinear(const double *F, int H, int W, int C, double u, double v,
+                  double *val, double *du, double *dv);
+
+/* DSM height and gradient (per metre) at world (x, y) */
+void orc_dsm(const orc_frame *f, double x, double y, double *h, double *hx, double *hy);
+
+/* Photo residual of anchor j at level l: r (C), dense Jacobian J (C*6,
+ * row-major), weight w.  Returns 1 if visible, 0 otherwise (r, J untouched). */
+int orc_photo_point(const orc_frame *f, int l, const double T[12], int j,
+                    double *r, double *J, double *w);
+
+/* gravity residual r (3) and Jacobian J (3*6) */
+void orc_gravity(const orc_frame *f, const double T[12], double r[3], double J[18]);
+
+/* laser-range residual and Jacobian (1*6) */
+void orc_range(const orc_frame *f, const double T[12], double *r, double J[6]);
+
+/* total objective at level l and its Gauss-Newton system:
+ * H (6*6), g (6) = J^T W r, cost, number of visible anchors */
+void orc_linearize(const orc_frame *f, int l, const double T[12],
+                   double H[36], double g[6], double *cost, int *nvalid);
+
+/* (A) x = b for a 6x6 SPD A by Cholesky; returns 0, or -1 if not PD */
+int orc_cholesky_solve6(const double A[36], const double b[6], double x[6]);
+
+/* LM over hypotheses [m0, m1) of poses_in (M*12).  Outputs are indexed by m.
+ * trace (optional): per hypothesis `trace_stride` rows of 4 doubles
+ * (level, cost before, candidate cost or NaN, accepted 0/1), one row per
+ * iteration; unused rows are NaN. */
+void orc_solve(const orc_frame *f, const double *poses_in, int m0, int m1,
+               double *poses_out, double *cost, int *iterations, int *status,
+               double *trace, int trace_stride);
+
+/* lowest finite cost among non-degenerate hypotheses, ties -> lowest index,
+ * -1 if none */
+int orc_best(const double *cost, const int *status, int M);
+
+void orc_set_threads(int n);
+int orc_get_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,370 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics
+(closed forms, library routines, finite differences, the synthetic scene's
+own ground truth).  CPU only."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+from scipy.spatial.transform import Rotation
+
+import oracle
+from synth import frames as S
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def small_frame(noise=True, seed=5, N=96, M=3, levels=((60, 80, 16), (120, 160, 32)), iters=(8, 8)):
+    return S.make_frame(2, 0, noise=noise, N=N, M=M, level_shapes=levels, iters=iters,
+                        dsm_side=128, seed=seed)
+
+
+def rand_pose(rng, scale_t=1.0, scale_r=0.3):
+    return oracle.se3_exp(np.concatenate([rng.normal(0, scale_t, 3), rng.normal(0, scale_r, 3)]))
+
+
+def left_perturb(T, d):
+    return oracle.compose(oracle.se3_exp(d), T)
+
+
+def mask_cell_edges(frame, pose, eps=1e-3):
+    """ref_w = 0 for anchors whose projection lies within eps px of a pixel
+    row/column or of the image border at any level (the bilinear gradient
+    jumps there, so finite differences across it are meaningless)."""
+    R = pose[:9].reshape(3, 3)
+    for L in frame.levels:
+        P = np.stack([L.x, L.y, L.z], 1).astype(np.float64)
+        X = P @ R.T + pose[9:]
+        u = L.K[0] * X[:, 0] / X[:, 2] + L.K[2]
+        v = L.K[1] * X[:, 1] / X[:, 2] + L.K[3]
+        near = (np.abs(u - np.round(u)) < eps) | (np.abs(v - np.round(v)) < eps)
+        w = np.ones(len(u), np.float32) if L.ref_w is None else L.ref_w.copy()
+        w[near] = 0.0
+        L.ref_w = w
+    return frame
+
+
+# ---------------------------------------------------------------- SE(3)
+def test_exp_matches_matrix_exponential():
+    rng = np.random.default_rng(0)
+    for scale in (1e-9, 1e-5, 1e-3, 0.1, 1.0, 3.0):
+        xi = np.concatenate([rng.normal(0, 5, 3), rng.normal(0, scale, 3)])
+        T = oracle.se3_exp(xi)
+        tw = np.zeros((4, 4))
+        w = xi[3:]
+        tw[:3, :3] = [[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]]
+        tw[:3, 3] = xi[:3]
+        E = scipy.linalg.expm(tw)
+        assert np.allclose(T[:9].reshape(3, 3), E[:3, :3], atol=1e-13, rtol=0)
+        assert np.allclose(T[9:], E[:3, 3], atol=1e-12, rtol=0)
+        assert np.allclose(T[:9].reshape(3, 3), Rotation.from_rotvec(w).as_matrix(), atol=1e-13)
+
+
+def test_exp_log_round_trip_and_orthonormal():
+    rng = np.random.default_rng(1)
+    for scale in (0.0, 1e-8, 1e-4, 0.5, 2.0, 3.1):
+        xi = np.concatenate([rng.normal(0, 10, 3), rng.normal(0, 1, 3)])
+        if scale == 0.0:
+            xi[3:] = 0
+        else:
+            xi[3:] *= scale / np.linalg.norm(xi[3:])
+        T = oracle.se3_exp(xi)
+        R = T[:9].reshape(3, 3)
+        assert np.allclose(R.T @ R, np.eye(3), atol=1e-14)
+        assert abs(np.linalg.det(R) - 1) < 1e-14
+        assert np.allclose(oracle.se3_log(T), xi, atol=1e-12 * max(1, np.abs(xi).max()))
+
+
+def test_exp_small_angle_branch_is_continuous():
+    w = np.array([0.3, -0.2, 0.9])
+    w /= np.linalg.norm(w)
+    rho = np.array([2.0, -1.0, 0.5])
+    a = oracle.se3_exp(np.concatenate([rho, w * (1e-4 * (1 - 1e-9))]))
+    b = oracle.se3_exp(np.concatenate([rho, w * (1e-4 * (1 + 1e-9))]))
+    assert np.abs(a - b).max() < 1e-12
+
+
+def test_compose_is_matrix_product():
+    rng = np.random.default_rng(2)
+    A, B = rand_pose(rng), rand_pose(rng)
+
+    def m4(T):
+        M = np.eye(4)
+        M[:3, :3] = T[:9].reshape(3, 3)
+        M[:3, 3] = T[9:]
+        return M
+    AB = oracle.compose(A, B)
+    assert np.allclose(m4(AB), m4(A) @ m4(B), atol=1e-14)
+
+
+# ---------------------------------------------------------------- losses
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_robust_derivative_and_values(kind):
+    b = 0.37
+    for s in (1e-4, 0.1, 0.37, 0.5, 3.0, 40.0):
+        rho, d = oracle.robust(kind, b, s)
+        h = 1e-6 * max(s, 1e-3)
+        fd = (oracle.robust(kind, b, s + h)[0] - oracle.robust(kind, b, s - h)[0]) / (2 * h)
+        if kind == 1 and abs(s - b) < 2 * h:
+            continue
+        assert abs(fd - d) < 1e-6 * max(1, abs(d))
+    if kind == 0:
+        assert abs(oracle.robust(0, b, b)[0] - b * math.log(2)) < 1e-15
+    if kind == 1:
+        lo, hi = oracle.robust(1, b, b * (1 - 1e-12))[0], oracle.robust(1, b, b * (1 + 1e-12))[0]
+        assert abs(lo - hi) < 1e-10
+        assert oracle.robust(1, b, 4 * b)[0] == pytest.approx(3 * b, rel=1e-14)
+
+
+# ---------------------------------------------------------------- bilinear
+def test_bilinear_exact_on_affine_fields():
+    rng = np.random.default_rng(3)
+    H, W, C = 7, 9, 5
+    a, b, c = rng.normal(size=C), rng.normal(size=C), rng.normal(size=C)
+    vv, uu = np.mgrid[0:H, 0:W]
+    F = uu[..., None] * a + vv[..., None] * b + c
+    for u, v in [(0.0, 0.0), (8.0, 6.0), (3.25, 2.5), (7.999, 0.001), (4.0, 3.0)]:
+        val, du, dv = oracle.bilinear(F, u, v)
+        assert np.allclose(val, a * u + b * v + c, atol=1e-13)
+        assert np.allclose(du, a, atol=1e-13)
+        assert np.allclose(dv, b, atol=1e-13)
+
+
+def test_bilinear_integer_coordinates_and_cell_derivatives():
+    rng = np.random.default_rng(4)
+    F = rng.normal(size=(6, 8, 3))
+    for (u, v) in [(0, 0), (3, 2), (7, 5), (6, 5)]:
+        val, _, _ = oracle.bilinear(F, float(u), float(v))
+        assert np.array_equal(val, F[v, u])
+    u, v = 2.3, 3.6
+    val, du, dv = oracle.bilinear(F, u, v)
+    h = 1e-6
+    fu = (oracle.bilinear(F, u + h, v)[0] - oracle.bilinear(F, u - h, v)[0]) / (2 * h)
+    fv = (oracle.bilinear(F, u, v + h)[0] - oracle.bilinear(F, u, v - h)[0]) / (2 * h)
+    assert np.allclose(fu, du, atol=1e-8) and np.allclose(fv, dv, atol=1e-8)
+
+
+# ---------------------------------------------------------------- projection
+def test_projection_closed_form_through_affine_features():
+    """With an affine descriptor field and zero reference, the residual
+    channels read back (u, v): pins the pinhole of Eq. (1)."""
+    f = small_frame(N=4, M=1, levels=((40, 60, 2),), iters=(1,))
+    L = f.levels[0]
+    vv, uu = np.mgrid[0:L.H, 0:L.W]
+    L.feat = np.stack([uu, vv], -1).astype(np.float32)
+    L.K = (50.0, 40.0, 29.5, 19.5)
+    L.x[:] = [0.0, 1.0, -2.0, 0.5]
+    L.y[:] = [0.0, 2.0, 1.0, -1.0]
+    L.z[:] = [10.0, 10.0, 20.0, 5.0]
+    L.ref = np.zeros((4, 2), np.float32)
+    of = oracle.OracleFrame(f)
+    T = np.concatenate([np.eye(3).ravel(), np.zeros(3)])
+    for j, (x, y, z) in enumerate([(0, 0, 10), (1, 2, 10), (-2, 1, 20), (0.5, -1, 5)]):
+        ok, r, J, w = oracle.photo_point(of, 0, T, j)
+        assert ok and w == 1.0
+        assert r[0] == pytest.approx(50.0 * x / z + 29.5, abs=1e-12)
+        assert r[1] == pytest.approx(40.0 * y / z + 19.5, abs=1e-12)
+    # a translated camera: X_cam = X + t
+    T2 = T.copy()
+    T2[9:] = [1.0, -1.0, 10.0]
+    ok, r, _, _ = oracle.photo_point(of, 0, T2, 1)
+    assert r[0] == pytest.approx(50.0 * 2.0 / 20.0 + 29.5) and r[1] == pytest.approx(40.0 * 1.0 / 20.0 + 19.5)
+    # behind the camera / outside the image -> not visible
+    T3 = T.copy()
+    T3[9:] = [0, 0, -30.0]
+    assert not oracle.photo_point(of, 0, T3, 0)[0]
+    T4 = T.copy()
+    T4[9:] = [100.0, 0, 0]
+    assert not oracle.photo_point(of, 0, T4, 0)[0]
+
+
+def test_out_of_view_penalty():
+    f = small_frame(N=8, M=1, levels=((40, 60, 4),), iters=(1,))
+    f.use_gravity = f.use_range = 0
+    T = f.gt_pose.copy()
+    T[9:] += [0, 0, -1e4]                       # everything behind the camera
+    of = oracle.OracleFrame(f)
+    H, g, c, n = oracle.linearize(of, 0, T)
+    b = f.levels[0].loss[1]
+    assert n == 0 and np.all(H == 0) and np.all(g == 0)
+    assert c == pytest.approx(8 * b * math.log1p(2.0 / b), rel=1e-14)
+
+
+# ---------------------------------------------------------------- Jacobians
+def fd_jacobian(fun, T, h=1e-6):
+    cols = []
+    for k in range(6):
+        d = np.zeros(6)
+        d[k] = h
+        cols.append((np.atleast_1d(fun(left_perturb(T, d))) - np.atleast_1d(fun(left_perturb(T, -d)))) / (2 * h))
+    return np.stack(cols, -1)
+
+
+def test_photo_jacobian_matches_finite_differences():
+    f = small_frame()
+    of = oracle.OracleFrame(f)
+    rng = np.random.default_rng(6)
+    T = left_perturb(f.gt_pose, np.concatenate([rng.normal(0, 0.5, 3), rng.normal(0, 0.005, 3)]))
+    mask_cell_edges(f, T, eps=1e-2)
+    checked = 0
+    for l in range(2):
+        for j in range(f.levels[l].N):
+            if f.levels[l].ref_w[j] == 0:
+                continue
+            ok, r, J, w = oracle.photo_point(of, l, T, j)
+            if not ok:
+                continue
+            Jfd = fd_jacobian(lambda X: oracle.photo_point(of, l, X, j)[1], T, h=1e-7)
+            assert np.allclose(J, Jfd, atol=1e-5 * max(1, np.abs(J).max()))
+            checked += 1
+    assert checked > 100
+
+
+def test_gravity_zero_at_truth_null_space_and_fd():
+    f = small_frame(noise=False)
+    of = oracle.OracleFrame(f)
+    r, J = oracle.gravity(of, f.gt_pose)
+    assert np.abs(r).max() < 1e-14
+    T = left_perturb(f.gt_pose, np.array([0.3, -0.1, 0.2, 0.02, -0.03, 0.01]))
+    r, J = oracle.gravity(of, T)
+    assert np.allclose(J, fd_jacobian(lambda X: oracle.gravity(of, X)[0], T), atol=1e-8)
+    gc = T[:9].reshape(3, 3) @ np.array(f.g_world)
+    assert np.abs(J @ np.concatenate([np.zeros(3), gc])).max() < 1e-14     # yaw about gravity
+    assert np.abs(J[:, :3]).max() == 0.0                                  # no translation
+
+
+def test_range_zero_at_truth_and_fd():
+    f = small_frame(noise=False)
+    of = oracle.OracleFrame(f)
+    r, J = oracle.range_term(of, f.gt_pose)
+    assert abs(r) < 1e-7
+    T = left_perturb(f.gt_pose, np.array([0.3, -0.1, 0.2, 0.002, -0.003, 0.001]))
+    r, J = oracle.range_term(of, T)
+    assert np.allclose(J, fd_jacobian(lambda X: oracle.range_term(of, X)[0], T, h=1e-7)[0], atol=1e-5)
+
+
+def test_dsm_lookup_against_raster():
+    f = small_frame()
+    of = oracle.OracleFrame(f)
+    D = f.dsm
+    for (i, j) in [(0, 0), (5, 7), (127, 127), (60, 3)]:
+        h, _, _ = oracle.dsm(of, D.x0 + j * D.gsd, D.y0 + i * D.gsd)
+        assert h == pytest.approx(float(D.heights[i, j]), abs=1e-12)
+    h, hx, hy = oracle.dsm(of, D.x0 - 100.0, D.y0 + 3 * D.gsd)        # clamped in x
+    assert h == pytest.approx(float(D.heights[3, 0])) and hx == 0.0
+
+
+# ---------------------------------------------------------------- normal equations
+def total_cost(of, l, T):
+    return oracle.linearize(of, l, T)[2]
+
+
+@pytest.mark.parametrize("loss", [0, 1, 2])
+def test_gradient_is_half_cost_gradient(loss):
+    """Gauss-Newton with IRLS weights: g = J^T W r = 1/2 d(cost)/d(xi)."""
+    f = small_frame(seed=11)
+    rng = np.random.default_rng(7)
+    T = left_perturb(f.gt_pose, np.concatenate([rng.normal(0, 0.8, 3), rng.normal(0, 0.008, 3)]))
+    mask_cell_edges(f, T, eps=5e-3)
+    for L in f.levels:
+        L.loss = (loss, L.loss[1])
+    f.gravity_loss = (loss, f.gravity_loss[1])
+    f.range_loss = (loss, f.range_loss[1])
+    f.lambda_range = 5.0          # make the prior terms visible in the sum
+    f.lambda_imu = 500.0
+    of = oracle.OracleFrame(f)
+    for l in range(2):
+        H, g, c, n = oracle.linearize(of, l, T)
+        fd = fd_jacobian(lambda X: total_cost(of, l, X), T, h=1e-7)[0]
+        assert np.allclose(g, 0.5 * fd, rtol=1e-5, atol=1e-6 * np.abs(g).max())
+
+
+def test_hessian_is_jtwj_with_fd_jacobian():
+    f = small_frame(N=16, seed=12)
+    rng = np.random.default_rng(8)
+    T = left_perturb(f.gt_pose, np.concatenate([rng.normal(0, 0.5, 3), rng.normal(0, 0.005, 3)]))
+    mask_cell_edges(f, T, eps=1e-2)
+    f.lambda_range = 3.0
+    of = oracle.OracleFrame(f)
+    l = 1
+    L = f.levels[l]
+    Href = np.zeros((6, 6))
+    for j in range(L.N):
+        ok, r, J, w = oracle.photo_point(of, l, T, j)
+        if not ok:
+            continue
+        Jfd = fd_jacobian(lambda X: oracle.photo_point(of, l, X, j)[1], T, h=1e-7)
+        s = w * float(r @ r)
+        Href += oracle.robust(L.loss[0], L.loss[1], s)[1] * w * Jfd.T @ Jfd
+    rg, _ = oracle.gravity(of, T)
+    Jg = fd_jacobian(lambda X: oracle.gravity(of, X)[0], T)
+    Href += f.lambda_imu * oracle.robust(*f.gravity_loss, float(rg @ rg))[1] * Jg.T @ Jg
+    rr, _ = oracle.range_term(of, T)
+    Jr = fd_jacobian(lambda X: oracle.range_term(of, X)[0], T, h=1e-7)
+    Href += f.lambda_range * oracle.robust(*f.range_loss, rr * rr)[1] * Jr.T @ Jr
+    H, g, c, n = oracle.linearize(of, l, T)
+    assert np.allclose(H, Href, rtol=1e-5, atol=1e-6 * np.abs(H).max())
+
+
+def test_cholesky_matches_lapack():
+    rng = np.random.default_rng(9)
+    for _ in range(20):
+        A = rng.normal(size=(6, 6))
+        A = A @ A.T + 1e-3 * np.eye(6)
+        b = rng.normal(size=6)
+        rc, x = oracle.cholesky_solve6(A, b)
+        assert rc == 0
+        assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-9, atol=1e-12)
+    A = np.diag([1.0, 1, 1, 1, 1, -1e-3])
+    assert oracle.cholesky_solve6(A, np.ones(6))[0] == -1
+
+
+# ---------------------------------------------------------------- LM
+def test_noise_free_frames_converge_to_ground_truth():
+    for cfg, kw in [(1, {}), (2, dict(N=512, M=1, level_shapes=((60, 80, 16), (120, 160, 32), (240, 320, 32)),
+                                      iters=(15, 15, 15)))]:
+        f = S.make_frame(cfg, 0, noise=False, **kw)
+        r = oracle.solve(f, threads=4)
+        te, re = S.pose_errors(r["poses"], f.gt_pose)
+        assert te[0] < 1e-6 and re[0] < 1e-6, (cfg, te, re)
+        assert r["status"][0] == oracle.CONVERGED
+
+
+def test_accepted_costs_never_increase():
+    f = S.make_frame(2, 3, N=400, M=6, level_shapes=((60, 80, 16), (120, 160, 32)), iters=(25, 25))
+    f.lm["step_tol_t"] = f.lm["step_tol_r"] = 0.0        # run every iteration
+    r = oracle.solve(f, threads=4, trace=True)
+    tr = r["trace"]
+    for m in range(tr.shape[0]):
+        rows = tr[m][~np.isnan(tr[m][:, 0])]
+        for lvl in np.unique(rows[:, 0]):
+            R = rows[rows[:, 0] == lvl]
+            cur = R[:, 1]
+            assert np.all(np.diff(cur) <= 0)
+            acc = R[:, 3] == 1
+            assert np.all(R[acc, 2] < R[acc, 1])
+            assert np.all(R[~acc & ~np.isnan(R[:, 2]), 2] >= R[~acc & ~np.isnan(R[:, 2]), 1])
+
+
+def test_selection_rule():
+    cost = np.array([3.0, np.nan, 1.0, 1.0, 0.5])
+    st = np.array([1, 1, 0, 1, 3], np.int32)
+    import ctypes as C
+    b = oracle.lib().orc_best(cost.ctypes.data_as(C.POINTER(C.c_double)), st.ctypes.data_as(C.POINTER(C.c_int)), 5)
+    assert b == 2
+
+
+# ---------------------------------------------------------------- paper constants
+def test_paper_hypothesis_grid():
+    gold = json.load(open(os.path.join(HERE, "golden", "paper_constants.json")))
+    g = gold["hypothesis_grid"]
+    offs = S.paper_grid_offsets()
+    assert len(offs) == g["count"] == 1210
+    assert len(set((round(a, 9), round(b, 9), round(c, 12)) for a, b, c in offs)) == 1210
+    yaws = sorted(set(round(math.degrees(c), 9) for _, _, c in offs))
+    assert yaws == sorted([s * a for a in g["yaw_offsets_deg"] for s in (1, -1)])
+    xs = sorted(set(round(a, 9) for a, _, _ in offs))
+    assert xs[0] == -g["xy_range_m"] and xs[-1] == g["xy_range_m"] and len(xs) == 11
+    assert sum(gold["schedule"]["iters_coarse_to_fine"]) == gold["schedule"]["unrolled_steps"]
