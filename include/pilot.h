@@ -1,0 +1,235 @@
+/*
+ * pilot.h -- C ABI of the MI355X (gfx950) sensor-prior featuremetric pose
+ * solver: the multi-hypothesis, coarse-to-fine Levenberg-Marquardt
+ * refinement of PiLoT v2 (arXiv 2606.31098), Method "Cross-View Learning",
+ * "Multi-Sensor Prior Fusion" and "Multi-Sensor Optimization" (Eqs. (1)-(9)),
+ * supplement "Multi-Hypothesis Refinement" and "Sensor-Prior Fusion in LM".
+ *
+ * Plain C: device pointers and sizes only, no framework types.  Every
+ * function returns PILOT_OK (0) or a negative error code; nothing throws
+ * across the ABI and nothing aborts the process.  On error,
+ * pilot_last_error() names the offending field or the HIP failure.
+ * Validation happens on the host before any launch: an EINVAL call launches
+ * nothing.  Numerical trouble of one hypothesis (too few visible anchors,
+ * non-finite values) is reported as its status, not as an error.
+ *
+ * Conventions
+ *   pose       world->camera, double[12]: R row-major (9) then t (3),
+ *              X_cam = R X_world + t (camera x right, y down, z forward).
+ *   update     T <- Exp(dxi) T, dxi = (rho; omega), translation first
+ *              (Eq. (9), applied as a left perturbation in the camera frame).
+ *   pixels     integer coordinates are pixel centres; anchor j is visible
+ *              at a level iff Z > z_min and 0 <= u <= W-1, 0 <= v <= H-1.
+ *   features   channels-last H x W x C (f32, or bf16 bit patterns), already
+ *              L2-normalised by the caller; reference descriptors N x C in the
+ *              same dtype; both rounded to bf16 once by the caller if bf16.
+ *   DSM        Hd x Wd f32 heights; sample (i, j) at (x0 + j gsd, y0 + i gsd),
+ *              bilinear with clamp-to-edge (Eq. (6)).
+ *   objective  per level l: sum_j rho_l(s_j) with s_j = w_j |r_j|^2
+ *              (Eqs. (1)-(2)), w_j = ref_w[j] * qconf(u, v); anchors outside
+ *              the view add rho_l(2 ref_w[j]); plus lambda_imu rho_g(|r_imu|^2)
+ *              (Eq. (3)) and lambda_range rho_r(r_range^2) (Eqs. (4)-(6)),
+ *              Eq. (7).  Normal equations use IRLS weights rho'(s)
+ *              (Gauss-Newton), so g = J^T W r = 1/2 grad(cost).
+ *   LM         per level: lambda = tau max diag H at the level's first
+ *              linearisation; a step that lowers the total cost is accepted
+ *              (lambda /= down, floor lambda_min_rel max diag H), otherwise
+ *              rejected (lambda *= up; reaching lambda_max_rel max diag H
+ *              stops the level, STALLED); an accepted step with
+ *              |d rho| < step_tol_t and |d omega| < step_tol_r ends the level
+ *              (CONVERGED); every iteration, accepted or not, counts.
+ *   selection  best = lowest final cost among non-degenerate hypotheses,
+ *              ties to the lowest index, -1 if none.
+ *
+ * Threading: a pilot_ctx is used by one host thread at a time; several
+ * contexts may share a device.  All work is enqueued on the context's stream
+ * and is asynchronous: outputs are valid once the caller has synchronised
+ * that stream.  The caller keeps every input alive until then.
+ */
+#ifndef PILOT_H
+#define PILOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PILOT_MAX_LEVELS 4
+#define PILOT_ABI_VERSION 1
+
+enum {
+    PILOT_OK = 0,
+    PILOT_EINVAL = -1,        /* bad argument; message names the field      */
+    PILOT_ENOMEM = -2,        /* workspace would exceed the HBM budget       */
+    PILOT_EDEVICE = -3,       /* HIP runtime failure; message carries it     */
+    PILOT_EAGAIN = -4,        /* serving: no slot or budget free right now   */
+    PILOT_EUNSUPPORTED = -5   /* valid request this build does not handle    */
+};
+
+enum { PILOT_F32 = 0, PILOT_BF16 = 1 };
+enum { PILOT_LOSS_CAUCHY = 0, PILOT_LOSS_HUBER = 1, PILOT_LOSS_L2 = 2 };
+enum { PILOT_CONVERGED = 0, PILOT_MAX_ITERS = 1, PILOT_STALLED = 2, PILOT_DEGENERATE = 3 };
+
+/* pilot_config.flags */
+enum {
+    PILOT_FLAG_NO_GRAPH = 1,  /* launch kernels directly instead of replaying a hipGraph */
+    PILOT_FLAG_AUTOTUNE = 2,  /* time tile candidates on first use of a shape class     */
+    PILOT_FLAG_PROFILE = 4    /* time every pass launch with hipEvents (implies NO_GRAPH) */
+};
+
+typedef struct pilot_ctx pilot_ctx;
+
+typedef struct {
+    int32_t device;             /* HIP device ordinal                                   */
+    int32_t flags;              /* PILOT_FLAG_*                                         */
+    void *stream;               /* hipStream_t for all work; NULL = null stream         */
+    size_t hbm_budget_bytes;    /* cap on workspace + admitted serving frames; 0 = none */
+    const char *tune_cache;     /* autotune cache file (read at create, appended); NULL */
+    int32_t max_slots;          /* serving slots; 0 = 64                                */
+    int32_t reserved;
+} pilot_config;
+
+/* One pyramid level (Eq. (1) at level l, scaled intrinsics K_l). */
+typedef struct {
+    int32_t H, W, C;            /* C in {16, 32, 64, 128, 256}; H, W >= 2             */
+    int32_t dtype;              /* PILOT_F32 or PILOT_BF16, for feat and ref         */
+    const void *feat;           /* device, H*W*C, channels-last                      */
+    const float *qconf;         /* device, H*W query confidence, or NULL (= 1)       */
+    double K[4];                /* fx, fy, cx, cy of this level                      */
+    int32_t N;                  /* anchors (>= 0)                                    */
+    const float *x, *y, *z;     /* device, N each: world points (may be shared)      */
+    const void *ref;            /* device, N*C reference descriptors                 */
+    const float *ref_w;         /* device, N per-anchor weight >= 0, or NULL (= 1)   */
+    int32_t iters;              /* LM iterations at this level (0..1000)             */
+    int32_t loss_kind;          /* PILOT_LOSS_*                                      */
+    double loss_scale;          /* b > 0                                              */
+} pilot_level;
+
+typedef struct {
+    int32_t n_levels;           /* 1..PILOT_MAX_LEVELS, coarse -> fine                */
+    pilot_level level[PILOT_MAX_LEVELS];
+    int32_t M;                  /* hypotheses (1..65536)                              */
+    const double *poses_in;     /* device, M*12                                       */
+    /* gravity prior, Eq. (3) */
+    int32_t use_gravity;
+    int32_t gravity_loss_kind;
+    double g_imu[3];            /* measured gravity direction, camera frame           */
+    double g_world[3];          /* gravity direction, world frame (e.g. 0,0,-1)       */
+    double lambda_imu;          /* >= 0                                               */
+    double gravity_loss_scale;
+    /* laser range prior, Eqs. (4)-(6) */
+    int32_t use_range;
+    int32_t range_loss_kind;
+    double d_range;             /* metres, > 0                                        */
+    double pc[2];               /* range pixel on the finest level                    */
+    double lambda_range;        /* >= 0                                               */
+    double range_loss_scale;
+    const float *dsm;           /* device, Hd*Wd (required when use_range)            */
+    int32_t Hd, Wd;
+    double dsm_x0, dsm_y0, dsm_gsd;
+    /* Levenberg-Marquardt control */
+    double tau, lambda_up, lambda_down, lambda_min_rel, lambda_max_rel;
+    double step_tol_t, step_tol_r, z_min;
+    int32_t min_valid;          /* fewer visible anchors at a level start: DEGENERATE */
+    int32_t reserved;
+} pilot_frame;
+
+/* Caller-owned device buffers. */
+typedef struct {
+    double *poses_out;          /* M*12 final poses                                   */
+    double *cost;               /* M final total cost (finest level)                  */
+    int32_t *iterations;        /* M iterations executed, all levels                  */
+    int32_t *status;            /* M PILOT_CONVERGED .. PILOT_DEGENERATE              */
+    int32_t *best;              /* 1 index (or -1)                                    */
+} pilot_result;
+
+typedef struct {
+    uint64_t pairs[PILOT_MAX_LEVELS];      /* anchor x hypothesis evaluations, per level  */
+    uint64_t pair_bytes[PILOT_MAX_LEVELS]; /* algorithmic gathered bytes (4 C s_f/pair)   */
+    uint64_t launches[PILOT_MAX_LEVELS];   /* pass launches per level                     */
+    double pass_ms[PILOT_MAX_LEVELS];      /* summed pass durations (PILOT_FLAG_PROFILE)  */
+    uint64_t timed_launches[PILOT_MAX_LEVELS];
+    uint64_t graph_replays, graph_captures;
+} pilot_stats;
+
+/* Create a context on cfg->device using cfg->stream.  *out is NULL on error;
+ * the message is then available from pilot_last_error(NULL) (per thread). */
+int pilot_create(pilot_ctx **out, const pilot_config *cfg);
+
+/* Release the context and its workspace (synchronises its stream first). */
+void pilot_destroy(pilot_ctx *ctx);
+
+/* Message of the last failed call on ctx (or of this thread when ctx is
+ * NULL); "" if none.  Valid until the next call on ctx. */
+const char *pilot_last_error(const pilot_ctx *ctx);
+
+/* Refine frames[0..n_frames) (each with its own hypotheses) coarse to fine
+ * and select the best hypothesis of each frame (multi-hypothesis LM of the
+ * Method's "Multi-Sensor Optimization").  results[i] receives frame i.
+ * Enqueued on the context stream; no host synchronisation inside. */
+int pilot_solve(pilot_ctx *ctx, const pilot_frame *frames, int n_frames,
+                const pilot_result *results);
+
+/* Diagnostic: the damped system's terms at given poses, without an LM step.
+ * For level `level` of `frame` and poses (device, frame->M*12): H21 (device,
+ * M*21, upper triangle of the 6x6 row by row), g6 (M*6), cost (M), nvalid
+ * (M visible anchors).  Total objective of Eq. (7) and its J^T W J,
+ * J^T W r of Eq. (8).  frame->poses_in is ignored. */
+int pilot_linearize(pilot_ctx *ctx, const pilot_frame *frame, int level,
+                    const double *poses, double *H21, double *g6, double *cost,
+                    int32_t *nvalid);
+
+/* ---------------------------------------------------------------------
+ * Serving (continuous batching).  A frame is admitted into a slot when a
+ * slot and HBM budget are free; pilot_step advances every active slot by
+ * one LM pass (each slot at its own level and iteration); pilot_poll
+ * reports completion and frees the slot.  Results are written to the
+ * result buffers given at admission.  Admission accounts the frame's input
+ * bytes (as declared by its sizes) plus its workspace against the budget.
+ * ------------------------------------------------------------------- */
+
+/* Bytes a frame would hold against the budget (inputs + workspace). */
+int pilot_admit_cost(pilot_ctx *ctx, const pilot_frame *frame, size_t *bytes);
+
+/* Admit a frame.  PILOT_EAGAIN (nothing enqueued) when no slot is free or
+ * the budget would be exceeded.  Hypotheses come from frame->poses_in,
+ * copied on the stream at admission (the caller may reuse that buffer after
+ * its stream passes this call). */
+int pilot_admit(pilot_ctx *ctx, const pilot_frame *frame, const pilot_result *result,
+                int *slot);
+
+/* One LM pass for every active slot (enqueued on the stream). */
+int pilot_step(pilot_ctx *ctx);
+
+/* 1 if the slot's frame has finished and its results are written (the slot
+ * is then free), 0 if still running, negative on error.  Reads a small
+ * device flag: synchronises with the work enqueued before it. */
+int pilot_poll(pilot_ctx *ctx, int slot);
+
+/* Number of active slots and budget bytes in use. */
+int pilot_serving_state(pilot_ctx *ctx, int *active_slots, size_t *bytes_in_use);
+
+/* Counters since creation (or the last reset). */
+int pilot_get_stats(pilot_ctx *ctx, pilot_stats *out, int reset);
+
+/* Autotune the pass kernel for the shapes of `frame` now (times candidate
+ * tile configurations with hipEvents on the stream); the choice is cached
+ * per shape class and appended to the tune cache file. */
+int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame);
+
+/* "G=8 PPG=8 BPC=2" style description of the tile choice for a level shape. */
+int pilot_tile_choice(pilot_ctx *ctx, int C, int dtype, int N, int M, char *buf, int buflen);
+
+int pilot_abi_version(void);
+
+/* sizeof of an ABI struct by name ("pilot_frame", "pilot_level",
+ * "pilot_result", "pilot_config", "pilot_stats"); 0 if unknown.  Lets a
+ * binding check its struct layout against the library's. */
+size_t pilot_sizeof(const char *name);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PILOT_H */

@@ -231,9 +231,9 @@ void orc_dsm(const orc_frame *f, double x, double y, double *h, double *hx, doub
     double fj = (x - f->dsm_x0) / f->dsm_gsd;
     double fi = (y - f->dsm_y0) / f->dsm_gsd;
     int cj = 0, ci = 0;
-    if (fj < 0.0) { fj = 0.0; cj = 1; }
+    if (!(fj >= 0.0)) { fj = 0.0; cj = 1; }          /* also NaN */
     if (fj > f->Wd - 1.0) { fj = f->Wd - 1.0; cj = 1; }
-    if (fi < 0.0) { fi = 0.0; ci = 1; }
+    if (!(fi >= 0.0)) { fi = 0.0; ci = 1; }
     if (fi > f->Hd - 1.0) { fi = f->Hd - 1.0; ci = 1; }
     int j0 = (int)floor(fj), i0 = (int)floor(fi);
     if (j0 > f->Wd - 2) j0 = f->Wd - 2;

@@ -1,0 +1,123 @@
+// pilot_device.h -- device-side layout shared by the host runtime and the
+// gfx950 kernels of libpilot (internal; not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pilot {
+
+constexpr int kMaxLevels = 4;
+constexpr int kBlock = 256;      // threads per pass block (4 wave64)
+// Per-hypothesis partial record (floats): 21 H, 6 g, count, then the cost as
+// an FP64 bit pattern in two slots, 1 pad.
+constexpr int kNV = 32;
+constexpr int kNSum = 28;        // float sums: 21 H + 6 g + visible count
+constexpr int kCostSlot = 28;    // FP64 cost occupies slots 28, 29
+
+// One pyramid level of one frame, as the pass kernel reads it.
+struct LevelDev {
+    const void *feat;
+    const float *qconf;
+    const float *x, *y, *z;
+    const void *ref;
+    const float *ref_w;
+    double fx, fy, cx, cy;
+    int H, W, C, N;
+    int iters, loss_kind;
+    float loss_b;
+    int dtype;
+};
+
+// One frame (solve) or one serving slot.
+struct FrameDev {
+    LevelDev lv[kMaxLevels];
+    int n_levels, M, hyp_base, slot;
+    // gravity prior
+    int use_g, grav_kind;
+    double grav_b, lam_imu;
+    double g_imu[3], g_world[3];
+    // range prior; q = d_range * unit ray of the range pixel (camera frame)
+    int use_r, range_kind;
+    double range_b, lam_range;
+    double q[3];
+    const float *dsm;
+    int Hd, Wd;
+    double dsm_x0, dsm_y0, dsm_gsd;
+    // LM control
+    double tau, up, down, lmin_rel, lmax_rel, tol_t, tol_r;
+    float z_min;
+    int min_valid;
+    const double *poses_in;
+    // outputs
+    double *poses_out, *cost_out;
+    int *iters_out, *status_out, *best_out;
+    // diagnostic outputs (pilot_linearize)
+    double *diag_H, *diag_g, *diag_cost;
+    int *diag_n;
+    int *done_flag;   // serving: set to 1 by the finalize step
+    int pad0, pad1;
+};
+
+// A tile of G hypotheses x P anchors of one frame at one level.
+struct WorkItem {
+    int frame;       // index into the FrameDev table
+    int htile;       // hypothesis tile (G hypotheses)
+    int ptile;       // anchor tile (P anchors)
+    int pad;
+};
+
+// A hypothesis tile of one frame and the run of work items holding its partials.
+struct TileItem {
+    int frame;
+    int htile;
+    int first_item;  // item index of anchor tile 0
+    int n_ptiles;
+};
+
+// LM state of one hypothesis (FP64 master pose and damped system).
+struct HypState {
+    double T[12];    // accepted pose
+    double Tc[12];   // candidate under evaluation
+    double dxi[6];   // step that produced Tc
+    double H[21];    // system at T (upper triangle, row by row)
+    double g[6];
+    double cost, lam, lmin, lmax;
+    int level, phase, it_level, it_total, status, nvalid, pad0, pad1;
+};
+
+enum { PHASE_START = 0, PHASE_CAND = 1 };
+enum { ST_CONVERGED = 0, ST_MAX_ITERS = 1, ST_STALLED = 2, ST_DEGENERATE = 3 };
+enum { MODE_LM = 0, MODE_DIAG = 1 };
+
+// Pose a hypothesis is evaluated at in the next pass: R row-major (9), t (3),
+// 4 pad -> 128 bytes.
+struct PoseEval {
+    double v[16];
+};
+
+struct PassArgs {
+    const FrameDev *frames;
+    const WorkItem *items;
+    int n_items;
+    int level;
+    const PoseEval *pose;
+    const int *hlev;             // level whose evaluation is pending; -1 finished
+    float *partials;             // [item][G][kNV]
+};
+
+struct EpilogueArgs {
+    const FrameDev *frames;
+    const TileItem *tiles;
+    int n_tiles;
+    int level;
+    int G;
+    int mode;                    // MODE_LM or MODE_DIAG
+    const float *partials;
+    PoseEval *pose;
+    int *hlev;
+    HypState *hs;
+    unsigned long long *pairs;   // evaluated anchor x hypothesis pairs of this launch's class
+};
+
+}  // namespace pilot

@@ -1,0 +1,37 @@
+// pilot_kernels.h -- launch entry points of the gfx950 kernels (internal).
+#pragma once
+
+#include "pilot_device.h"
+
+namespace pilot {
+
+struct TileConfig {
+    int G;      // lanes per anchor = hypotheses per tile (4, 8 or 16)
+    int PPG;    // anchors per lane group per work item
+    int grid;   // persistent grid size (blocks)
+};
+
+// True if a pass kernel exists for (C, dtype, G).
+bool pass_supported(int C, int dtype, int G);
+
+// One pass over `n_items` work items at `level`, every item a tile of
+// G hypotheses x (kBlock / G * PPG) anchors of frames with C channels:
+// writes the per-item partial sums.
+hipError_t launch_pass(int C, int dtype, const TileConfig &tc, const PassArgs &a, hipStream_t s);
+
+// Per hypothesis tile: FP64 reduction of the partials in item order and the
+// LM step (or, in MODE_DIAG, the diagnostic outputs).
+hipError_t launch_epilogue(const EpilogueArgs &e, hipStream_t s);
+
+// Initialise hypothesis state of frames[0..n_frames) from their poses_in
+// (mode LM) or from `diag_poses` at `diag_level` (mode DIAG, one frame).
+hipError_t launch_init(const FrameDev *frames, int n_frames, int max_M, HypState *hs,
+                       PoseEval *pose, int *hlev, int mode, const double *diag_poses,
+                       int diag_level, hipStream_t s);
+
+// Write results of every frame whose hypotheses have all finished and that
+// has not been finalised yet (done_flag == 0), including the argmin.
+hipError_t launch_finalize(const FrameDev *frames, int n_frames, const HypState *hs,
+                           const int *hlev, hipStream_t s);
+
+}  // namespace pilot

@@ -1,0 +1,219 @@
+// pilot_kernels.hip -- hypothesis-state initialisation, result finalisation
+// (with the best-hypothesis selection) and the pass-kernel dispatch.
+#include "pilot_kernels.h"
+#include "pilot_lm.h"
+
+namespace pilot {
+
+hipError_t launch_pass_c16(int, const TileConfig &, const PassArgs &, hipStream_t);
+hipError_t launch_pass_c32(int, const TileConfig &, const PassArgs &, hipStream_t);
+hipError_t launch_pass_c64(int, const TileConfig &, const PassArgs &, hipStream_t);
+hipError_t launch_pass_c128(int, const TileConfig &, const PassArgs &, hipStream_t);
+hipError_t launch_pass_c256(int, const TileConfig &, const PassArgs &, hipStream_t);
+
+bool pass_supported(int C, int dtype, int G)
+{
+    if (dtype != 0 && dtype != 1) return false;
+    if (G != 4 && G != 8 && G != 16) return false;
+    return C == 16 || C == 32 || C == 64 || C == 128 || C == 256;
+}
+
+hipError_t launch_pass(int C, int dtype, const TileConfig &tc, const PassArgs &a, hipStream_t s)
+{
+    switch (C) {
+    case 16: return launch_pass_c16(dtype, tc, a, s);
+    case 32: return launch_pass_c32(dtype, tc, a, s);
+    case 64: return launch_pass_c64(dtype, tc, a, s);
+    case 128: return launch_pass_c128(dtype, tc, a, s);
+    case 256: return launch_pass_c256(dtype, tc, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+constexpr int kMaxG = 16;
+
+// One block per hypothesis tile: sums the tile's per-item partials in FP64
+// in item order (fixed, independent of what else shares the launch), then
+// one thread per hypothesis adds the prior terms and advances its LM state
+// (or writes the diagnostic system).
+__global__ __launch_bounds__(256) void epilogue_kernel(EpilogueArgs e)
+{
+    __shared__ double s_sum[kMaxG][kNV];
+    const TileItem ti = e.tiles[blockIdx.x];
+    const FrameDev *f = e.frames + ti.frame;
+    const int G = e.G;
+    const int h0 = ti.htile * G;
+    const int hb = f->hyp_base + h0;
+    const int nh = min(G, f->M - h0);
+    unsigned act = 0;
+    for (int hh = 0; hh < nh; ++hh) act |= (e.hlev[hb + hh] == e.level ? 1u : 0u) << hh;
+    if (act == 0) return;
+    const int stride = G * kNV;
+    for (int t = threadIdx.x; t < stride; t += blockDim.x) {
+        const int hh = t / kNV, v = t - hh * kNV;
+        const float *src = e.partials + (size_t)ti.first_item * stride + t;
+        double s = 0.0;
+        if (v < kNSum) {
+            for (int it = 0; it < ti.n_ptiles; ++it) s += (double)src[(size_t)it * stride];
+        } else if (v == kCostSlot) {
+            for (int it = 0; it < ti.n_ptiles; ++it) {
+                const float *q = src + (size_t)it * stride;
+                const unsigned long long bits = (unsigned long long)__float_as_uint(q[0]) |
+                                                ((unsigned long long)__float_as_uint(q[1]) << 32);
+                s += __longlong_as_double((long long)bits);
+            }
+        }
+        s_sum[hh][v] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicAdd(e.pairs, (unsigned long long)__popc(act) * (unsigned long long)f->lv[e.level].N);
+    const int t = threadIdx.x;
+    if (t >= G || !((act >> t) & 1u)) return;
+    const int gh = hb + t;
+    const int m = h0 + t;
+    const double *S = s_sum[t];
+    if (e.mode == MODE_DIAG) {
+        double Hd[21], gd[6];
+        for (int i = 0; i < 21; ++i) Hd[i] = S[i];
+        for (int i = 0; i < 6; ++i) gd[i] = S[21 + i];
+        double cost = S[kCostSlot];
+        add_priors(*f, e.hs[gh].T, Hd, gd, cost);
+        for (int i = 0; i < 21; ++i) f->diag_H[(size_t)m * 21 + i] = Hd[i];
+        for (int i = 0; i < 6; ++i) f->diag_g[(size_t)m * 6 + i] = gd[i];
+        f->diag_cost[m] = cost;
+        f->diag_n[m] = (int)S[27];
+        e.hlev[gh] = -1;
+    } else {
+        HypState s = e.hs[gh];
+        PoseEval p = e.pose[gh];
+        int hl = e.level;
+        lm_advance(*f, s, S, p, hl);
+        e.hs[gh] = s;
+        e.pose[gh] = p;
+        e.hlev[gh] = hl;
+    }
+}
+
+hipError_t launch_epilogue(const EpilogueArgs &e, hipStream_t s)
+{
+    if (e.G > kMaxG) return hipErrorInvalidValue;
+    if (e.n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(epilogue_kernel, dim3(e.n_tiles), dim3(256), 0, s, e);
+    return hipGetLastError();
+}
+
+// One thread per hypothesis; blockIdx.y selects the frame.
+__global__ __launch_bounds__(256) void init_kernel(const FrameDev *frames, HypState *hs, PoseEval *pose,
+                                                    int *hlev, int mode, const double *dposes, int dlevel)
+{
+    const FrameDev &f = frames[blockIdx.y];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && f.done_flag) *f.done_flag = 0;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= f.M) return;
+    const int gh = f.hyp_base + m;
+    const double *src = (mode == MODE_DIAG) ? dposes + (size_t)12 * m : f.poses_in + (size_t)12 * m;
+    HypState s;
+    bool finite = true;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        s.T[i] = src[i];
+        s.Tc[i] = src[i];
+        finite = finite && isfinite(src[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        s.dxi[i] = 0.0;
+        s.g[i] = 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 21; ++i) s.H[i] = 0.0;
+    s.cost = __longlong_as_double(0x7ff8000000000000LL);   // NaN until evaluated
+    s.lam = s.lmin = s.lmax = 0.0;
+    s.level = (mode == MODE_DIAG) ? dlevel : 0;
+    s.phase = PHASE_START;
+    s.it_level = s.it_total = 0;
+    s.status = finite ? ST_MAX_ITERS : ST_DEGENERATE;
+    s.nvalid = 0;
+    s.pad0 = s.pad1 = 0;
+    hs[gh] = s;
+    PoseEval p;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) p.v[i] = src[i];
+#pragma unroll
+    for (int i = 12; i < 16; ++i) p.v[i] = 0.0;
+    pose[gh] = p;
+    hlev[gh] = finite ? s.level : -1;
+}
+
+hipError_t launch_init(const FrameDev *frames, int n_frames, int max_M, HypState *hs, PoseEval *pose,
+                       int *hlev, int mode, const double *diag_poses, int diag_level, hipStream_t s)
+{
+    dim3 grid((max_M + 255) / 256, n_frames), block(256);
+    hipLaunchKernelGGL(init_kernel, grid, block, 0, s, frames, hs, pose, hlev, mode, diag_poses, diag_level);
+    return hipGetLastError();
+}
+
+// One block per frame.  Writes poses, costs, iterations and statuses and the
+// index of the lowest final cost among non-degenerate hypotheses (NaN never
+// wins, ties go to the lowest index) once every hypothesis has finished.
+__global__ __launch_bounds__(256) void finalize_kernel(const FrameDev *frames, const HypState *hs,
+                                                        const int *hlev)
+{
+    const FrameDev &f = frames[blockIdx.x];
+    __shared__ double s_cost[256];
+    __shared__ int s_idx[256];
+    __shared__ int s_skip;
+    if (threadIdx.x == 0) s_skip = (f.done_flag && *f.done_flag) ? 1 : 0;
+    __syncthreads();
+    if (s_skip) return;
+    int pending = 0;
+    for (int m = threadIdx.x; m < f.M; m += blockDim.x) pending |= (hlev[f.hyp_base + m] != -1);
+    if (__syncthreads_or(pending)) return;
+
+    double bc = 0.0;
+    int bi = -1;
+    for (int m = threadIdx.x; m < f.M; m += blockDim.x) {
+        const HypState &s = hs[f.hyp_base + m];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) f.poses_out[(size_t)12 * m + i] = s.T[i];
+        f.cost_out[m] = s.cost;
+        f.iters_out[m] = s.it_total;
+        f.status_out[m] = s.status;
+        if (s.status != ST_DEGENERATE && isfinite(s.cost) && (bi < 0 || s.cost < bc)) {
+            bc = s.cost;
+            bi = m;
+        }
+    }
+    s_cost[threadIdx.x] = bc;
+    s_idx[threadIdx.x] = bi;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) {
+            const int j = threadIdx.x + w;
+            const int ia = s_idx[threadIdx.x], ib = s_idx[j];
+            if (ib >= 0 && (ia < 0 || s_cost[j] < s_cost[threadIdx.x] ||
+                            (s_cost[j] == s_cost[threadIdx.x] && ib < ia))) {
+                s_cost[threadIdx.x] = s_cost[j];
+                s_idx[threadIdx.x] = ib;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *f.best_out = s_idx[0];
+        if (f.done_flag) {
+            __threadfence_system();
+            *f.done_flag = 1;
+        }
+    }
+}
+
+hipError_t launch_finalize(const FrameDev *frames, int n_frames, const HypState *hs, const int *hlev,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_frames), dim3(256), 0, s, frames, hs, hlev);
+    return hipGetLastError();
+}
+
+}  // namespace pilot

@@ -1,0 +1,315 @@
+// pilot_lm.h -- per-hypothesis FP64 epilogue of one LM pass (device code):
+// gravity and laser-range prior terms, the damped 6x6 Cholesky solve, the
+// SE(3) update and the Levenberg-Marquardt accept/reject control.
+#pragma once
+
+#include "pilot_device.h"
+
+namespace pilot {
+
+// index of (a, b), a <= b, in the row-by-row upper triangle of a 6x6
+__host__ __device__ constexpr int tri(int a, int b) { return a * 6 - a * (a - 1) / 2 + (b - a); }
+
+__device__ __forceinline__ void robust_f64(int kind, double b, double s, double &rho, double &drho)
+{
+    if (kind == 0) {                       // Cauchy
+        rho = b * log1p(s / b);
+        drho = 1.0 / (1.0 + s / b);
+    } else if (kind == 1) {                // Huber
+        if (s <= b) {
+            rho = s;
+            drho = 1.0;
+        } else {
+            double r = sqrt(b * s);
+            rho = 2.0 * r - b;
+            drho = b / r;
+        }
+    } else {
+        rho = s;
+        drho = 1.0;
+    }
+}
+
+// SE(3) exponential of xi = (rho, omega): rotation by Rodrigues' formula,
+// translation V rho (left Jacobian of SO(3)); Taylor coefficients near 0.
+__device__ inline void se3_exp(const double xi[6], double E[12])
+{
+    const double wx = xi[3], wy = xi[4], wz = xi[5];
+    const double t2 = wx * wx + wy * wy + wz * wz;
+    double a, b, c;
+    if (t2 < 1e-8) {
+        a = 1.0 - t2 * (1.0 / 6.0) + t2 * t2 * (1.0 / 120.0);
+        b = 0.5 - t2 * (1.0 / 24.0) + t2 * t2 * (1.0 / 720.0);
+        c = (1.0 / 6.0) - t2 * (1.0 / 120.0) + t2 * t2 * (1.0 / 5040.0);
+    } else {
+        const double t = sqrt(t2);
+        double s, co;
+        sincos(t, &s, &co);
+        a = s / t;
+        b = (1.0 - co) / t2;
+        c = (t - s) / (t2 * t);
+    }
+    // W = [w]x ; W^2 = w w^T - t2 I
+    const double W2[9] = {wx * wx - t2, wx * wy, wx * wz,
+                          wy * wx, wy * wy - t2, wy * wz,
+                          wz * wx, wz * wy, wz * wz - t2};
+    const double W[9] = {0.0, -wz, wy, wz, 0.0, -wx, -wy, wx, 0.0};
+    double V[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double I = (i == 0 || i == 4 || i == 8) ? 1.0 : 0.0;
+        E[i] = I + a * W[i] + b * W2[i];
+        V[i] = I + b * W[i] + c * W2[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) E[9 + i] = V[3 * i] * xi[0] + V[3 * i + 1] * xi[1] + V[3 * i + 2] * xi[2];
+}
+
+// out = A * B for world->camera poses
+__device__ inline void se3_mul(const double A[12], const double B[12], double out[12])
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            out[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+        out[9 + i] = A[3 * i] * B[9] + A[3 * i + 1] * B[10] + A[3 * i + 2] * B[11] + A[9 + i];
+    }
+}
+
+// (H + lam I) x = -g by Cholesky; false if a pivot is not positive/finite.
+__device__ inline bool damped_solve(const double H[21], const double g[6], double lam, double x[6])
+{
+    double L[21];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            double s = H[tri(j, i)] + (i == j ? lam : 0.0);
+#pragma unroll
+            for (int k = 0; k < j; ++k) s -= L[tri(k, i)] * L[tri(k, j)];
+            if (i == j) {
+                if (!(s > 0.0) || !isfinite(s)) return false;
+                L[tri(i, i)] = sqrt(s);
+            } else {
+                L[tri(j, i)] = s / L[tri(j, j)];
+            }
+        }
+    }
+    // L stored transposed in the upper triangle: L(i,k) = L[tri(k, i)]
+    double y[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double s = -g[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= L[tri(k, i)] * y[k];
+        y[i] = s / L[tri(i, i)];
+    }
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+        double s = y[i];
+#pragma unroll
+        for (int k = i + 1; k < 6; ++k) s -= L[tri(i, k)] * x[k];
+        x[i] = s / L[tri(i, i)];
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        if (!isfinite(x[i])) return false;
+    return true;
+}
+
+// Bilinear DSM height and gradient (per metre), clamp-to-edge.
+__device__ inline void dsm_lookup(const FrameDev &f, double x, double y, double &h, double &hx, double &hy)
+{
+    double fj = (x - f.dsm_x0) / f.dsm_gsd, fi = (y - f.dsm_y0) / f.dsm_gsd;
+    const bool cj = !(fj >= 0.0 && fj <= f.Wd - 1.0), ci = !(fi >= 0.0 && fi <= f.Hd - 1.0);
+    fj = fmin(fmax(fj, 0.0), f.Wd - 1.0);
+    fi = fmin(fmax(fi, 0.0), f.Hd - 1.0);
+    const int j0 = min((int)fj, f.Wd - 2), i0 = min((int)fi, f.Hd - 2);
+    const double a = fj - j0, b = fi - i0;
+    const float *row0 = f.dsm + (size_t)i0 * f.Wd + j0;
+    const float *row1 = row0 + f.Wd;
+    const double d00 = row0[0], d01 = row0[1], d10 = row1[0], d11 = row1[1];
+    const double top = d00 + a * (d01 - d00), bot = d10 + a * (d11 - d10);
+    h = top + b * (bot - top);
+    hx = cj ? 0.0 : ((d01 - d00) + b * ((d11 - d10) - (d01 - d00))) / f.dsm_gsd;
+    hy = ci ? 0.0 : (bot - top) / f.dsm_gsd;
+}
+
+// Add the gravity (Eq. (3)) and laser-range (Eqs. (4)-(6)) terms at pose T.
+__device__ inline void add_priors(const FrameDev &f, const double T[12], double H[21], double g[6], double &cost)
+{
+    if (f.use_g) {
+        double gc[3], r[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            gc[i] = T[3 * i] * f.g_world[0] + T[3 * i + 1] * f.g_world[1] + T[3 * i + 2] * f.g_world[2];
+            r[i] = gc[i] - f.g_imu[i];
+        }
+        double rho, drho;
+        robust_f64(f.grav_kind, f.grav_b, r[0] * r[0] + r[1] * r[1] + r[2] * r[2], rho, drho);
+        cost += f.lam_imu * rho;
+        const double W = f.lam_imu * drho;
+        // J = [0 | -[gc]x]:  J^T J = |gc|^2 I - gc gc^T,  J^T r = gc x r  (rotation block)
+        const double n2 = gc[0] * gc[0] + gc[1] * gc[1] + gc[2] * gc[2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = a; b < 3; ++b) H[tri(3 + a, 3 + b)] += W * ((a == b ? n2 : 0.0) - gc[a] * gc[b]);
+        g[3] += W * (gc[1] * r[2] - gc[2] * r[1]);
+        g[4] += W * (gc[2] * r[0] - gc[0] * r[2]);
+        g[5] += W * (gc[0] * r[1] - gc[1] * r[0]);
+    }
+    if (f.use_r) {
+        const double qt[3] = {f.q[0] - T[9], f.q[1] - T[10], f.q[2] - T[11]};
+        double P[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) P[i] = T[i] * qt[0] + T[3 + i] * qt[1] + T[6 + i] * qt[2];   // R^T qt
+        double h, hx, hy;
+        dsm_lookup(f, P[0], P[1], h, hx, hy);
+        const double r = P[2] - h;
+        double rho, drho;
+        robust_f64(f.range_kind, f.range_b, r * r, rho, drho);
+        cost += f.lam_range * rho;
+        const double W = f.lam_range * drho;
+        // dr/dP = a = (-hx, -hy, 1); J = [-R a, (R a) x q]
+        double Ra[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) Ra[i] = -T[3 * i] * hx - T[3 * i + 1] * hy + T[3 * i + 2];
+        const double J[6] = {-Ra[0], -Ra[1], -Ra[2],
+                             Ra[1] * f.q[2] - Ra[2] * f.q[1],
+                             Ra[2] * f.q[0] - Ra[0] * f.q[2],
+                             Ra[0] * f.q[1] - Ra[1] * f.q[0]};
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+#pragma unroll
+            for (int b = a; b < 6; ++b) H[tri(a, b)] += W * J[a] * J[b];
+            g[a] += W * J[a] * r;
+        }
+    }
+}
+
+__device__ inline void store_pose(PoseEval &p, const double T[12])
+{
+#pragma unroll
+    for (int i = 0; i < 12; ++i) p.v[i] = T[i];
+}
+
+// Finish the hypothesis' current level with status `st`: move to the next
+// level's start (re-evaluated at the accepted pose) or finish.
+__device__ inline void level_done(const FrameDev &f, HypState &s, int st, PoseEval &p32, int &hlev)
+{
+    s.status = st;
+    if (s.level + 1 < f.n_levels) {
+        s.level += 1;
+        s.phase = PHASE_START;
+        store_pose(p32, s.T);
+        hlev = s.level;
+    } else {
+        hlev = -1;
+    }
+}
+
+// Solve for the next candidate (consuming iterations on failed
+// factorisations) or end the level when iterations or damping run out.
+__device__ inline void propose(const FrameDev &f, HypState &s, PoseEval &p32, int &hlev)
+{
+    const int iters = f.lv[s.level].iters;
+    for (;;) {
+        if (s.it_level >= iters) {
+            level_done(f, s, ST_MAX_ITERS, p32, hlev);
+            return;
+        }
+        s.it_level += 1;
+        s.it_total += 1;
+        double dx[6];
+        if (!damped_solve(s.H, s.g, s.lam, dx)) {
+            s.lam *= f.up;
+            if (s.lam >= s.lmax) {
+                level_done(f, s, ST_STALLED, p32, hlev);
+                return;
+            }
+            continue;
+        }
+        double E[12];
+        se3_exp(dx, E);
+        se3_mul(E, s.T, s.Tc);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) s.dxi[i] = dx[i];
+        s.phase = PHASE_CAND;
+        store_pose(p32, s.Tc);
+        hlev = s.level;
+        return;
+    }
+}
+
+// Consume one evaluation (photo sums S: H21, g6, count, cost) of the
+// hypothesis at its pending pose and advance its LM state.
+__device__ inline void lm_advance(const FrameDev &f, HypState &s, const double *S, PoseEval &p32, int &hlev)
+{
+    double H[21], g[6];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) H[i] = S[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) g[i] = S[21 + i];
+    double cost = S[kCostSlot];
+    const int n = (int)S[27];
+    const double *Tp = (s.phase == PHASE_START) ? s.T : s.Tc;
+    add_priors(f, Tp, H, g, cost);
+
+    bool finite = isfinite(cost);
+#pragma unroll
+    for (int i = 0; i < 21; ++i) finite = finite && isfinite(H[i]);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) finite = finite && isfinite(g[i]);
+
+    if (s.phase == PHASE_START) {
+        double D = 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) D = fmax(D, H[tri(i, i)]);
+        s.cost = cost;
+        s.nvalid = n;
+        if (n < f.min_valid || !finite || !(D > 0.0)) {
+            s.status = ST_DEGENERATE;
+            hlev = -1;
+            return;
+        }
+#pragma unroll
+        for (int i = 0; i < 21; ++i) s.H[i] = H[i];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) s.g[i] = g[i];
+        s.lam = f.tau * D;
+        s.lmin = f.lmin_rel * D;
+        s.lmax = f.lmax_rel * D;
+        s.it_level = 0;
+        propose(f, s, p32, hlev);
+        return;
+    }
+    // candidate evaluation
+    if (finite && cost < s.cost) {
+#pragma unroll
+        for (int i = 0; i < 12; ++i) s.T[i] = s.Tc[i];
+#pragma unroll
+        for (int i = 0; i < 21; ++i) s.H[i] = H[i];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) s.g[i] = g[i];
+        s.cost = cost;
+        s.nvalid = n;
+        s.lam = fmax(s.lam / f.down, s.lmin);
+        const double nt = sqrt(s.dxi[0] * s.dxi[0] + s.dxi[1] * s.dxi[1] + s.dxi[2] * s.dxi[2]);
+        const double nr = sqrt(s.dxi[3] * s.dxi[3] + s.dxi[4] * s.dxi[4] + s.dxi[5] * s.dxi[5]);
+        if (nt < f.tol_t && nr < f.tol_r) {
+            level_done(f, s, ST_CONVERGED, p32, hlev);
+            return;
+        }
+    } else {
+        s.lam *= f.up;
+        if (s.lam >= s.lmax) {
+            level_done(f, s, ST_STALLED, p32, hlev);
+            return;
+        }
+    }
+    propose(f, s, p32, hlev);
+}
+
+}  // namespace pilot

@@ -1,0 +1,7 @@
+// Pass kernels for C = 256 channels (f32 and bf16; G = 4, 8, 16).
+#include "pilot_kernels.h"
+#include "pilot_pass.inc"
+
+namespace pilot {
+PILOT_INSTANTIATE_PASS(256)
+}  // namespace pilot

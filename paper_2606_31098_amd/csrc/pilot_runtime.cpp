@@ -1,0 +1,891 @@
+// pilot_runtime.cpp -- host runtime and C ABI of libpilot.
+//
+// A solve is planned on the host (validation, tile choice, work lists),
+// its descriptors are copied to the device once, and the whole
+// coarse-to-fine LM schedule -- init, then per level (1 + iters) x
+// [pass kernel -> epilogue kernel], then finalize -- is enqueued on the
+// context stream, replayed from a cached hipGraph when a solve with the same
+// plan shape was seen before.  No device->host traffic inside a solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/pilot.h"
+#include "pilot_kernels.h"
+
+using namespace pilot;
+
+namespace {
+
+thread_local std::string g_thread_err;
+
+constexpr int kStatClasses = 64;
+
+int class_index(int level, int C, int dtype)
+{
+    int ci = C == 16 ? 0 : C == 32 ? 1 : C == 64 ? 2 : C == 128 ? 3 : 4;
+    return level * 10 + ci * 2 + dtype;
+}
+
+int elem_size(int dtype) { return dtype == PILOT_BF16 ? 2 : 4; }
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+struct LaunchGroup {
+    int level, C, dtype;
+    TileConfig tc;
+    int item_off, n_items;
+    int tile_off, n_tiles;
+    int passes;
+    int stat_class;
+};
+
+struct Plan {
+    std::vector<FrameDev> frames;
+    std::vector<WorkItem> items;
+    std::vector<TileItem> tiles;
+    std::vector<LaunchGroup> groups;
+    int total_hyps = 0, max_M = 0, max_levels = 0;
+    size_t partial_floats = 0;
+    std::string key;
+};
+
+struct TimedLaunch {
+    hipEvent_t a, b;
+    int level, cls;
+};
+
+struct ServingSlot;
+
+}  // namespace
+
+struct pilot_ctx {
+    int device = 0;
+    int flags = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    size_t budget = 0;
+    std::string tune_cache;
+    int max_slots = 64;
+    int ncu = 256;
+    std::string err;
+
+    // workspace
+    DevBuf desc, hs, pose, hlev, partials, pairs;
+    size_t ws_bytes = 0;
+    unsigned generation = 0;
+
+    // pinned staging ring
+    struct Stage {
+        void *p = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+        bool pending = false;
+    } stage[2];
+    int stage_next = 0;
+
+    std::unordered_map<std::string, hipGraphExec_t> graphs;
+    std::map<std::string, TileConfig> tuned;
+
+    std::vector<TimedLaunch> timed;
+    std::vector<hipEvent_t> event_pool;
+    double pass_ms[kStatClasses] = {0};
+    uint64_t timed_launches[kStatClasses] = {0};
+    uint64_t launches[kStatClasses] = {0};
+    uint64_t graph_replays = 0, graph_captures = 0;
+};
+
+namespace {
+
+int fail(pilot_ctx *ctx, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx)
+        ctx->err = buf;
+    else
+        g_thread_err = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                       \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail((ctx), PILOT_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),   \
+                        __FILE__, __LINE__);                                                    \
+    } while (0)
+
+bool finite_all(const double *v, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// ---------------------------------------------------------------- validation
+int validate_frame(pilot_ctx *ctx, const pilot_frame *f, int fi, bool need_poses)
+{
+    if (!f) return fail(ctx, PILOT_EINVAL, "frames[%d]: NULL", fi);
+    if (f->n_levels < 1 || f->n_levels > PILOT_MAX_LEVELS)
+        return fail(ctx, PILOT_EINVAL, "frames[%d].n_levels: must be 1..%d (got %d)", fi, PILOT_MAX_LEVELS, f->n_levels);
+    if (f->M < 1 || f->M > 65536) return fail(ctx, PILOT_EINVAL, "frames[%d].M: must be 1..65536 (got %d)", fi, f->M);
+    if (need_poses && !f->poses_in) return fail(ctx, PILOT_EINVAL, "frames[%d].poses_in: NULL", fi);
+    for (int l = 0; l < f->n_levels; ++l) {
+        const pilot_level &L = f->level[l];
+        if (L.H < 2 || L.W < 2)
+            return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].H/W: must be >= 2 (got %dx%d)", fi, l, L.H, L.W);
+        if (L.dtype != PILOT_F32 && L.dtype != PILOT_BF16)
+            return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].dtype: must be PILOT_F32 or PILOT_BF16", fi, l);
+        if (L.C != 16 && L.C != 32 && L.C != 64 && L.C != 128 && L.C != 256) {
+            if (L.C > 0 && L.C % 8 == 0 && L.C <= 512)
+                return fail(ctx, PILOT_EUNSUPPORTED, "frames[%d].level[%d].C: %d channels has no kernel (16, 32, 64, 128, 256)", fi, l, L.C);
+            return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].C: must be 16, 32, 64, 128 or 256 (got %d)", fi, l, L.C);
+        }
+        if ((double)L.H * L.W * L.C >= 2147483647.0)
+            return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d]: H*W*C must be < 2^31", fi, l);
+        if (!L.feat) return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].feat: NULL", fi, l);
+        if (!aligned16(L.feat)) return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].feat: must be 16-byte aligned", fi, l);
+        if (!finite_all(L.K, 4) || !(L.K[0] > 0) || !(L.K[1] > 0))
+            return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].K: fx, fy must be > 0 and all finite", fi, l);
+        if (L.N < 0 || (double)L.N * L.C >= 2147483647.0)
+            return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].N: must be >= 0 with N*C < 2^31 (got %d)", fi, l, L.N);
+        if (L.N > 0) {
+            if (!L.x || !L.y || !L.z) return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].x/y/z: NULL", fi, l);
+            if (!L.ref) return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].ref: NULL", fi, l);
+            if (!aligned16(L.ref)) return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].ref: must be 16-byte aligned", fi, l);
+        }
+        if (L.iters < 0 || L.iters > 1000)
+            return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].iters: must be 0..1000 (got %d)", fi, l, L.iters);
+        if (L.loss_kind < 0 || L.loss_kind > 2)
+            return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].loss_kind: must be PILOT_LOSS_*", fi, l);
+        if (!(L.loss_scale > 0) || !std::isfinite(L.loss_scale))
+            return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].loss_scale: must be finite and > 0", fi, l);
+    }
+    if (f->use_gravity) {
+        if (!finite_all(f->g_imu, 3) || !finite_all(f->g_world, 3))
+            return fail(ctx, PILOT_EINVAL, "frames[%d].g_imu/g_world: must be finite", fi);
+        if (!(f->lambda_imu >= 0) || !std::isfinite(f->lambda_imu))
+            return fail(ctx, PILOT_EINVAL, "frames[%d].lambda_imu: must be finite and >= 0", fi);
+        if (f->gravity_loss_kind < 0 || f->gravity_loss_kind > 2 || !(f->gravity_loss_scale > 0) ||
+            !std::isfinite(f->gravity_loss_scale))
+            return fail(ctx, PILOT_EINVAL, "frames[%d].gravity_loss_kind/scale: invalid", fi);
+    }
+    if (f->use_range) {
+        if (!f->dsm) return fail(ctx, PILOT_EINVAL, "frames[%d].dsm: NULL with use_range", fi);
+        if (f->Hd < 2 || f->Wd < 2) return fail(ctx, PILOT_EINVAL, "frames[%d].Hd/Wd: must be >= 2", fi);
+        if (!(f->dsm_gsd > 0) || !std::isfinite(f->dsm_gsd) || !std::isfinite(f->dsm_x0) || !std::isfinite(f->dsm_y0))
+            return fail(ctx, PILOT_EINVAL, "frames[%d].dsm_x0/y0/gsd: invalid", fi);
+        if (!(f->d_range > 0) || !std::isfinite(f->d_range))
+            return fail(ctx, PILOT_EINVAL, "frames[%d].d_range: must be finite and > 0", fi);
+        if (!finite_all(f->pc, 2)) return fail(ctx, PILOT_EINVAL, "frames[%d].pc: must be finite", fi);
+        if (!(f->lambda_range >= 0) || !std::isfinite(f->lambda_range))
+            return fail(ctx, PILOT_EINVAL, "frames[%d].lambda_range: must be finite and >= 0", fi);
+        if (f->range_loss_kind < 0 || f->range_loss_kind > 2 || !(f->range_loss_scale > 0) ||
+            !std::isfinite(f->range_loss_scale))
+            return fail(ctx, PILOT_EINVAL, "frames[%d].range_loss_kind/scale: invalid", fi);
+    }
+    if (!(f->tau > 0) || !std::isfinite(f->tau)) return fail(ctx, PILOT_EINVAL, "frames[%d].tau: must be finite and > 0", fi);
+    if (!(f->lambda_up > 1) || !std::isfinite(f->lambda_up)) return fail(ctx, PILOT_EINVAL, "frames[%d].lambda_up: must be > 1", fi);
+    if (!(f->lambda_down >= 1) || !std::isfinite(f->lambda_down)) return fail(ctx, PILOT_EINVAL, "frames[%d].lambda_down: must be >= 1", fi);
+    if (!(f->lambda_min_rel >= 0) || !(f->lambda_max_rel > f->lambda_min_rel) || !std::isfinite(f->lambda_max_rel))
+        return fail(ctx, PILOT_EINVAL, "frames[%d].lambda_min_rel/lambda_max_rel: need 0 <= min < max < inf", fi);
+    if (!(f->step_tol_t >= 0) || !(f->step_tol_r >= 0) || !std::isfinite(f->step_tol_t) || !std::isfinite(f->step_tol_r))
+        return fail(ctx, PILOT_EINVAL, "frames[%d].step_tol_t/r: must be finite and >= 0", fi);
+    if (!(f->z_min >= 0) || !std::isfinite(f->z_min)) return fail(ctx, PILOT_EINVAL, "frames[%d].z_min: must be finite and >= 0", fi);
+    if (f->min_valid < 0) return fail(ctx, PILOT_EINVAL, "frames[%d].min_valid: must be >= 0", fi);
+    return PILOT_OK;
+}
+
+// ---------------------------------------------------------------- workspace
+int ensure(pilot_ctx *ctx, DevBuf &b, size_t bytes, bool zero = false)
+{
+    if (bytes <= b.cap) return PILOT_OK;
+    size_t want = std::max(bytes, b.cap + b.cap / 2);
+    want = (want + 4095) & ~(size_t)4095;
+    size_t total = ctx->ws_bytes - b.cap + want;
+    if (ctx->budget && total > ctx->budget) {
+        want = bytes;
+        total = ctx->ws_bytes - b.cap + want;
+        if (total > ctx->budget)
+            return fail(ctx, PILOT_ENOMEM, "workspace of %zu bytes exceeds the HBM budget of %zu bytes", total, ctx->budget);
+    }
+    if (b.p) {
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        HIPCHK(ctx, hipFree(b.p));
+        b.p = nullptr;
+    }
+    HIPCHK(ctx, hipMalloc(&b.p, want));
+    if (zero) HIPCHK(ctx, hipMemset(b.p, 0, want));
+    ctx->ws_bytes = total;
+    b.cap = want;
+    ctx->generation++;
+    return PILOT_OK;
+}
+
+void *stage_acquire(pilot_ctx *ctx, size_t bytes, int *which, int *rc)
+{
+    *rc = PILOT_OK;
+    pilot_ctx::Stage &s = ctx->stage[ctx->stage_next];
+    *which = ctx->stage_next;
+    ctx->stage_next ^= 1;
+    if (s.pending) {
+        hipError_t e = hipEventSynchronize(s.ev);
+        if (e != hipSuccess) {
+            *rc = fail(ctx, PILOT_EDEVICE, "hipEventSynchronize: %s", hipGetErrorString(e));
+            return nullptr;
+        }
+        s.pending = false;
+    }
+    if (bytes > s.cap) {
+        if (s.p) hipHostFree(s.p);
+        s.p = nullptr;
+        size_t want = std::max(bytes, (size_t)1 << 16);
+        hipError_t e = hipHostMalloc(&s.p, want, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            s.cap = 0;
+            *rc = fail(ctx, PILOT_EDEVICE, "hipHostMalloc: %s", hipGetErrorString(e));
+            return nullptr;
+        }
+        s.cap = want;
+    }
+    return s.p;
+}
+
+// ---------------------------------------------------------------- tiles
+int log2_bucket(int n)
+{
+    int b = 0;
+    while ((1 << (b + 1)) <= std::max(n, 1)) ++b;
+    return b;
+}
+
+std::string tune_key(int C, int dtype, int N, int M)
+{
+    std::ostringstream o;
+    o << "C" << C << "_d" << dtype << "_N" << log2_bucket(N) << "_M" << log2_bucket(M);
+    return o.str();
+}
+
+TileConfig heuristic_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M)
+{
+    TileConfig tc;
+    tc.G = (C == 16) ? 4 : 8;
+    const int NG = kBlock / tc.G;
+    const long ht = (M + tc.G - 1) / tc.G;
+    tc.PPG = 1;
+    for (int ppg : {16, 8, 4, 2, 1}) {
+        const long items = ht * std::max(1, (N + NG * ppg - 1) / (NG * ppg));
+        tc.PPG = ppg;
+        if (items >= 4L * ctx->ncu) break;
+    }
+    tc.grid = 0;   // one block per item
+    return tc;
+}
+
+TileConfig choose_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M)
+{
+    auto it = ctx->tuned.find(tune_key(C, dtype, N, M));
+    if (it != ctx->tuned.end()) return it->second;
+    return heuristic_tile(ctx, C, dtype, N, M);
+}
+
+int n_ptiles_of(const TileConfig &tc, int N)
+{
+    const int P = (kBlock / tc.G) * tc.PPG;
+    return std::max(1, (N + P - 1) / P);
+}
+
+int grid_of(const pilot_ctx *ctx, const TileConfig &tc, int n_items)
+{
+    if (tc.grid <= 0) return std::max(1, n_items);
+    return std::max(1, std::min(n_items, tc.grid * ctx->ncu));
+}
+
+void fill_frame_dev(FrameDev &d, const pilot_frame &f, const pilot_result *r, int hyp_base)
+{
+    memset(&d, 0, sizeof d);
+    for (int l = 0; l < f.n_levels; ++l) {
+        const pilot_level &L = f.level[l];
+        LevelDev &o = d.lv[l];
+        o.feat = L.feat;
+        o.qconf = L.qconf;
+        o.x = L.x;
+        o.y = L.y;
+        o.z = L.z;
+        o.ref = L.ref;
+        o.ref_w = L.ref_w;
+        o.fx = L.K[0];
+        o.fy = L.K[1];
+        o.cx = L.K[2];
+        o.cy = L.K[3];
+        o.H = L.H;
+        o.W = L.W;
+        o.C = L.C;
+        o.N = L.N;
+        o.iters = L.iters;
+        o.loss_kind = L.loss_kind;
+        o.loss_b = (float)L.loss_scale;
+        o.dtype = L.dtype;
+    }
+    d.n_levels = f.n_levels;
+    d.M = f.M;
+    d.hyp_base = hyp_base;
+    d.use_g = f.use_gravity ? 1 : 0;
+    d.grav_kind = f.gravity_loss_kind;
+    d.grav_b = f.gravity_loss_scale;
+    d.lam_imu = f.lambda_imu;
+    for (int i = 0; i < 3; ++i) {
+        d.g_imu[i] = f.g_imu[i];
+        d.g_world[i] = f.g_world[i];
+    }
+    d.use_r = f.use_range ? 1 : 0;
+    d.range_kind = f.range_loss_kind;
+    d.range_b = f.range_loss_scale;
+    d.lam_range = f.lambda_range;
+    {
+        // unit ray of the range pixel through the finest level's intrinsics (Eq. (4))
+        const pilot_level &Lf = f.level[f.n_levels - 1];
+        double ray[3] = {(f.pc[0] - Lf.K[2]) / Lf.K[0], (f.pc[1] - Lf.K[3]) / Lf.K[1], 1.0};
+        const double n = std::sqrt(ray[0] * ray[0] + ray[1] * ray[1] + ray[2] * ray[2]);
+        for (int i = 0; i < 3; ++i) d.q[i] = f.use_range ? f.d_range * ray[i] / n : 0.0;
+    }
+    d.dsm = f.dsm;
+    d.Hd = f.Hd;
+    d.Wd = f.Wd;
+    d.dsm_x0 = f.dsm_x0;
+    d.dsm_y0 = f.dsm_y0;
+    d.dsm_gsd = f.dsm_gsd;
+    d.tau = f.tau;
+    d.up = f.lambda_up;
+    d.down = f.lambda_down;
+    d.lmin_rel = f.lambda_min_rel;
+    d.lmax_rel = f.lambda_max_rel;
+    d.tol_t = f.step_tol_t;
+    d.tol_r = f.step_tol_r;
+    d.z_min = (float)f.z_min;
+    d.min_valid = f.min_valid;
+    d.poses_in = f.poses_in;
+    if (r) {
+        d.poses_out = r->poses_out;
+        d.cost_out = r->cost;
+        d.iters_out = r->iterations;
+        d.status_out = r->status;
+        d.best_out = r->best;
+    }
+}
+
+// Build the schedule: per level, frames grouped by (C, dtype), each group a
+// list of (hypothesis tile x anchor tile) work items.
+void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pilot_result *results,
+                int only_level, Plan &plan)
+{
+    plan.frames.resize(n);
+    int base = 0;
+    for (int i = 0; i < n; ++i) {
+        fill_frame_dev(plan.frames[i], frames[i], results ? &results[i] : nullptr, base);
+        base += frames[i].M;
+        plan.max_M = std::max(plan.max_M, frames[i].M);
+        plan.max_levels = std::max(plan.max_levels, frames[i].n_levels);
+    }
+    plan.total_hyps = base;
+    std::ostringstream key;
+    key << "n" << n << "_h" << base << "_m" << plan.max_M;
+    for (int l = 0; l < plan.max_levels; ++l) {
+        if (only_level >= 0 && l != only_level) continue;
+        std::map<std::pair<int, int>, std::vector<int>> by_class;
+        for (int i = 0; i < n; ++i)
+            if (l < frames[i].n_levels) by_class[{frames[i].level[l].C, frames[i].level[l].dtype}].push_back(i);
+        for (auto &kv : by_class) {
+            LaunchGroup g;
+            g.level = l;
+            g.C = kv.first.first;
+            g.dtype = kv.first.second;
+            // one tile shape per group, chosen for its largest frame
+            int Nmax = 0, Mmax = 0, iters = 0;
+            for (int i : kv.second) {
+                Nmax = std::max(Nmax, frames[i].level[l].N);
+                Mmax = std::max(Mmax, frames[i].M);
+                iters = std::max(iters, frames[i].level[l].iters);
+            }
+            g.tc = choose_tile(ctx, g.C, g.dtype, Nmax, Mmax);
+            g.item_off = (int)plan.items.size();
+            g.tile_off = (int)plan.tiles.size();
+            for (int i : kv.second) {
+                const int nht = (frames[i].M + g.tc.G - 1) / g.tc.G;
+                const int npt = n_ptiles_of(g.tc, frames[i].level[l].N);
+                for (int ht = 0; ht < nht; ++ht) {
+                    TileItem ti{i, ht, (int)plan.items.size() - g.item_off, npt};
+                    plan.tiles.push_back(ti);
+                    for (int pt = 0; pt < npt; ++pt) plan.items.push_back(WorkItem{i, ht, pt, 0});
+                }
+            }
+            g.n_items = (int)plan.items.size() - g.item_off;
+            g.n_tiles = (int)plan.tiles.size() - g.tile_off;
+            g.passes = (only_level >= 0) ? 1 : 1 + iters;
+            g.stat_class = class_index(l, g.C, g.dtype);
+            g.tc.grid = grid_of(ctx, g.tc, g.n_items);
+            plan.partial_floats = std::max(plan.partial_floats, (size_t)g.n_items * g.tc.G * kNV);
+            plan.groups.push_back(g);
+            key << "|l" << l << "c" << g.C << "d" << g.dtype << "G" << g.tc.G << "p" << g.tc.PPG << "g" << g.tc.grid
+                << "i" << g.n_items << "t" << g.n_tiles << "s" << g.passes;
+        }
+    }
+    plan.key = key.str();
+}
+
+hipEvent_t pool_event(pilot_ctx *ctx)
+{
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct DevPtrs {
+    FrameDev *frames;
+    WorkItem *items;
+    TileItem *tiles;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Copy the plan's descriptors to the device (pinned staging, async).
+int upload_plan(pilot_ctx *ctx, const Plan &plan, DevPtrs &dp)
+{
+    const size_t fb = align256(plan.frames.size() * sizeof(FrameDev));
+    const size_t ib = align256(std::max<size_t>(1, plan.items.size()) * sizeof(WorkItem));
+    const size_t tb = align256(std::max<size_t>(1, plan.tiles.size()) * sizeof(TileItem));
+    int rc = ensure(ctx, ctx->desc, fb + ib + tb);
+    if (rc) return rc;
+    int which;
+    char *h = (char *)stage_acquire(ctx, fb + ib + tb, &which, &rc);
+    if (!h) return rc;
+    memcpy(h, plan.frames.data(), plan.frames.size() * sizeof(FrameDev));
+    if (!plan.items.empty()) memcpy(h + fb, plan.items.data(), plan.items.size() * sizeof(WorkItem));
+    if (!plan.tiles.empty()) memcpy(h + fb + ib, plan.tiles.data(), plan.tiles.size() * sizeof(TileItem));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->desc.p, h, fb + ib + tb, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipEventRecord(ctx->stage[which].ev, ctx->stream));
+    ctx->stage[which].pending = true;
+    char *d = (char *)ctx->desc.p;
+    dp.frames = (FrameDev *)d;
+    dp.items = (WorkItem *)(d + fb);
+    dp.tiles = (TileItem *)(d + fb + ib);
+    return PILOT_OK;
+}
+
+int ensure_state(pilot_ctx *ctx, const Plan &plan)
+{
+    int rc;
+    const size_t H = std::max(1, plan.total_hyps);
+    if ((rc = ensure(ctx, ctx->hs, H * sizeof(HypState)))) return rc;
+    if ((rc = ensure(ctx, ctx->pose, H * sizeof(PoseEval)))) return rc;
+    if ((rc = ensure(ctx, ctx->hlev, H * sizeof(int)))) return rc;
+    if ((rc = ensure(ctx, ctx->partials, std::max<size_t>(1, plan.partial_floats) * sizeof(float)))) return rc;
+    if ((rc = ensure(ctx, ctx->pairs, kStatClasses * sizeof(unsigned long long), true))) return rc;
+    return PILOT_OK;
+}
+
+// Enqueue one pass (pass kernel + epilogue) of a launch group.
+int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const LaunchGroup &g, int mode,
+                 hipStream_t s, bool timed)
+{
+    PassArgs a;
+    a.frames = dp.frames;
+    a.items = dp.items + g.item_off;
+    a.n_items = g.n_items;
+    a.level = g.level;
+    a.pose = (const PoseEval *)ctx->pose.p;
+    a.hlev = (const int *)ctx->hlev.p;
+    a.partials = (float *)ctx->partials.p;
+    TimedLaunch tl{};
+    if (timed) {
+        tl.a = pool_event(ctx);
+        tl.b = pool_event(ctx);
+        tl.level = g.level;
+        tl.cls = g.stat_class;
+        if (!tl.a || !tl.b) return fail(ctx, PILOT_EDEVICE, "hipEventCreate failed");
+        HIPCHK(ctx, hipEventRecord(tl.a, s));
+    }
+    HIPCHK(ctx, launch_pass(g.C, g.dtype, g.tc, a, s));
+    if (timed) {
+        HIPCHK(ctx, hipEventRecord(tl.b, s));
+        ctx->timed.push_back(tl);
+    }
+    EpilogueArgs e;
+    e.frames = dp.frames;
+    e.tiles = dp.tiles + g.tile_off;
+    e.n_tiles = g.n_tiles;
+    e.level = g.level;
+    e.G = g.tc.G;
+    e.mode = mode;
+    e.partials = (const float *)ctx->partials.p;
+    e.pose = (PoseEval *)ctx->pose.p;
+    e.hlev = (int *)ctx->hlev.p;
+    e.hs = (HypState *)ctx->hs.p;
+    e.pairs = (unsigned long long *)ctx->pairs.p + g.stat_class;
+    HIPCHK(ctx, launch_epilogue(e, s));
+    ctx->launches[g.stat_class]++;
+    return PILOT_OK;
+}
+
+// The full LM schedule of a plan on stream s.
+int enqueue_schedule(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, hipStream_t s, bool timed)
+{
+    HIPCHK(ctx, launch_init(dp.frames, (int)plan.frames.size(), plan.max_M, (HypState *)ctx->hs.p,
+                            (PoseEval *)ctx->pose.p, (int *)ctx->hlev.p, MODE_LM, nullptr, 0, s));
+    for (int l = 0; l < plan.max_levels; ++l) {
+        int maxp = 0;
+        for (const LaunchGroup &g : plan.groups)
+            if (g.level == l) maxp = std::max(maxp, g.passes);
+        for (int k = 0; k < maxp; ++k)
+            for (const LaunchGroup &g : plan.groups)
+                if (g.level == l && k < g.passes) {
+                    int rc = enqueue_pass(ctx, plan, dp, g, MODE_LM, s, timed);
+                    if (rc) return rc;
+                }
+    }
+    HIPCHK(ctx, launch_finalize(dp.frames, (int)plan.frames.size(), (const HypState *)ctx->hs.p,
+                                (const int *)ctx->hlev.p, s));
+    return PILOT_OK;
+}
+
+void load_tune_cache(pilot_ctx *ctx)
+{
+    if (ctx->tune_cache.empty()) return;
+    std::ifstream in(ctx->tune_cache);
+    std::string key;
+    TileConfig tc;
+    while (in >> key >> tc.G >> tc.PPG >> tc.grid)
+        if (pass_supported(16, 0, tc.G) && tc.PPG >= 1 && tc.PPG <= 64) ctx->tuned[key] = tc;
+}
+
+int collect_timings(pilot_ctx *ctx)
+{
+    if (ctx->timed.empty()) return PILOT_OK;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (TimedLaunch &t : ctx->timed) {
+        float ms = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, t.a, t.b));
+        ctx->pass_ms[t.cls] += ms;
+        ctx->timed_launches[t.cls]++;
+        ctx->event_pool.push_back(t.a);
+        ctx->event_pool.push_back(t.b);
+    }
+    ctx->timed.clear();
+    return PILOT_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+extern "C" {
+
+int pilot_abi_version(void) { return PILOT_ABI_VERSION; }
+
+size_t pilot_sizeof(const char *name)
+{
+    if (!name) return 0;
+    if (!strcmp(name, "pilot_frame")) return sizeof(pilot_frame);
+    if (!strcmp(name, "pilot_level")) return sizeof(pilot_level);
+    if (!strcmp(name, "pilot_result")) return sizeof(pilot_result);
+    if (!strcmp(name, "pilot_config")) return sizeof(pilot_config);
+    if (!strcmp(name, "pilot_stats")) return sizeof(pilot_stats);
+    return 0;
+}
+
+const char *pilot_last_error(const pilot_ctx *ctx) { return ctx ? ctx->err.c_str() : g_thread_err.c_str(); }
+
+int pilot_create(pilot_ctx **out, const pilot_config *cfg)
+{
+    if (!out) return fail(nullptr, PILOT_EINVAL, "out: NULL");
+    *out = nullptr;
+    if (!cfg) return fail(nullptr, PILOT_EINVAL, "cfg: NULL");
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return fail(nullptr, PILOT_EDEVICE, "hipGetDeviceCount: %s", hipGetErrorString(e));
+    if (cfg->device < 0 || cfg->device >= ndev)
+        return fail(nullptr, PILOT_EINVAL, "cfg.device: %d is not one of the %d visible devices", cfg->device, ndev);
+    if (cfg->max_slots < 0 || cfg->max_slots > 4096) return fail(nullptr, PILOT_EINVAL, "cfg.max_slots: must be 0..4096");
+    e = hipSetDevice(cfg->device);
+    if (e != hipSuccess) return fail(nullptr, PILOT_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, cfg->device);
+    if (e != hipSuccess) return fail(nullptr, PILOT_EDEVICE, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, PILOT_EUNSUPPORTED, "device %d is %s; this library is built for gfx950", cfg->device, prop.gcnArchName);
+    pilot_ctx *ctx = new pilot_ctx();
+    ctx->device = cfg->device;
+    ctx->flags = cfg->flags;
+    if (ctx->flags & PILOT_FLAG_PROFILE) ctx->flags |= PILOT_FLAG_NO_GRAPH;
+    ctx->stream = (hipStream_t)cfg->stream;
+    ctx->budget = cfg->hbm_budget_bytes;
+    ctx->tune_cache = cfg->tune_cache ? cfg->tune_cache : "";
+    ctx->max_slots = cfg->max_slots ? cfg->max_slots : 64;
+    ctx->ncu = prop.multiProcessorCount;
+    e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->stage[0].ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->stage[1].ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        int rc = fail(nullptr, PILOT_EDEVICE, "stream/event creation: %s", hipGetErrorString(e));
+        pilot_destroy(ctx);
+        return rc;
+    }
+    load_tune_cache(ctx);
+    *out = ctx;
+    return PILOT_OK;
+}
+
+void pilot_destroy(pilot_ctx *ctx)
+{
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    hipStreamSynchronize(ctx->stream);
+    for (auto &kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+    for (auto &t : ctx->timed) {
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    for (hipEvent_t e : ctx->event_pool) hipEventDestroy(e);
+    for (auto &s : ctx->stage) {
+        if (s.ev) hipEventSynchronize(s.ev), hipEventDestroy(s.ev);
+        if (s.p) hipHostFree(s.p);
+    }
+    for (DevBuf *b : {&ctx->desc, &ctx->hs, &ctx->pose, &ctx->hlev, &ctx->partials, &ctx->pairs})
+        if (b->p) hipFree(b->p);
+    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+    delete ctx;
+}
+
+int pilot_solve(pilot_ctx *ctx, const pilot_frame *frames, int n_frames, const pilot_result *results)
+{
+    if (!ctx) return fail(nullptr, PILOT_EINVAL, "ctx: NULL");
+    ctx->err.clear();
+    if (!frames) return fail(ctx, PILOT_EINVAL, "frames: NULL");
+    if (n_frames < 1) return fail(ctx, PILOT_EINVAL, "n_frames: must be >= 1 (got %d)", n_frames);
+    if (!results) return fail(ctx, PILOT_EINVAL, "results: NULL");
+    long total = 0;
+    for (int i = 0; i < n_frames; ++i) {
+        int rc = validate_frame(ctx, &frames[i], i, true);
+        if (rc) return rc;
+        const pilot_result &r = results[i];
+        if (!r.poses_out || !r.cost || !r.iterations || !r.status || !r.best)
+            return fail(ctx, PILOT_EINVAL, "results[%d]: every output buffer must be non-NULL", i);
+        total += frames[i].M;
+    }
+    if (total > (1L << 24)) return fail(ctx, PILOT_EINVAL, "total hypotheses %ld exceed 2^24", total);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+
+    if (ctx->flags & PILOT_FLAG_AUTOTUNE) {
+        for (int i = 0; i < n_frames; ++i) {
+            bool need = false;
+            for (int l = 0; l < frames[i].n_levels; ++l) {
+                const pilot_level &L = frames[i].level[l];
+                if (!ctx->tuned.count(tune_key(L.C, L.dtype, L.N, frames[i].M))) need = true;
+            }
+            if (need) {
+                int rc = pilot_autotune(ctx, &frames[i]);
+                if (rc) return rc;
+            }
+        }
+    }
+
+    Plan plan;
+    build_plan(ctx, frames, n_frames, results, -1, plan);
+    int rc = ensure_state(ctx, plan);
+    if (rc) return rc;
+    DevPtrs dp;
+    if ((rc = upload_plan(ctx, plan, dp))) return rc;
+
+    if (ctx->flags & PILOT_FLAG_NO_GRAPH)
+        return enqueue_schedule(ctx, plan, dp, ctx->stream, (ctx->flags & PILOT_FLAG_PROFILE) != 0);
+
+    std::string key = plan.key + "#" + std::to_string(ctx->generation) + "#" + std::to_string((uintptr_t)dp.frames);
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        rc = enqueue_schedule(ctx, plan, dp, ctx->cap_stream, false);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+        if (rc) {
+            if (graph) hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(ctx, PILOT_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(ctx, PILOT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        if (ctx->graphs.size() >= 64) {
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+            for (auto &kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+            ctx->graphs.clear();
+        }
+        it = ctx->graphs.emplace(key, exec).first;
+        ctx->graph_captures++;
+    }
+    HIPCHK(ctx, hipGraphLaunch(it->second, ctx->stream));
+    ctx->graph_replays++;
+    return PILOT_OK;
+}
+
+int pilot_linearize(pilot_ctx *ctx, const pilot_frame *frame, int level, const double *poses, double *H21,
+                    double *g6, double *cost, int32_t *nvalid)
+{
+    if (!ctx) return fail(nullptr, PILOT_EINVAL, "ctx: NULL");
+    ctx->err.clear();
+    int rc = validate_frame(ctx, frame, 0, false);
+    if (rc) return rc;
+    if (level < 0 || level >= frame->n_levels)
+        return fail(ctx, PILOT_EINVAL, "level: must be 0..%d (got %d)", frame->n_levels - 1, level);
+    if (!poses) return fail(ctx, PILOT_EINVAL, "poses: NULL");
+    if (!H21 || !g6 || !cost || !nvalid) return fail(ctx, PILOT_EINVAL, "H21/g6/cost/nvalid: NULL");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    Plan plan;
+    build_plan(ctx, frame, 1, nullptr, level, plan);
+    FrameDev &d = plan.frames[0];
+    d.diag_H = H21;
+    d.diag_g = g6;
+    d.diag_cost = cost;
+    d.diag_n = nvalid;
+    if ((rc = ensure_state(ctx, plan))) return rc;
+    DevPtrs dp;
+    if ((rc = upload_plan(ctx, plan, dp))) return rc;
+    HIPCHK(ctx, launch_init(dp.frames, 1, plan.max_M, (HypState *)ctx->hs.p, (PoseEval *)ctx->pose.p,
+                            (int *)ctx->hlev.p, MODE_DIAG, poses, level, ctx->stream));
+    for (const LaunchGroup &g : plan.groups)
+        if ((rc = enqueue_pass(ctx, plan, dp, g, MODE_DIAG, ctx->stream, (ctx->flags & PILOT_FLAG_PROFILE) != 0)))
+            return rc;
+    return PILOT_OK;
+}
+
+int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
+{
+    if (!ctx) return fail(nullptr, PILOT_EINVAL, "ctx: NULL");
+    int rc = validate_frame(ctx, frame, 0, true);
+    if (rc) return rc;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    for (int l = 0; l < frame->n_levels; ++l) {
+        const pilot_level &L = frame->level[l];
+        const std::string key = tune_key(L.C, L.dtype, L.N, frame->M);
+        if (ctx->tuned.count(key)) continue;
+        TileConfig best{};
+        float best_ms = 1e30f;
+        for (int G : {4, 8, 16}) {
+            if (L.C / G < 1) continue;
+            for (int ppg : {2, 4, 8, 16}) {
+                for (int bpc : {0, 2, 4}) {
+                    TileConfig tc{G, ppg, bpc};
+                    ctx->tuned[key] = tc;
+                    Plan plan;
+                    build_plan(ctx, frame, 1, nullptr, l, plan);
+                    if ((rc = ensure_state(ctx, plan))) return rc;
+                    DevPtrs dp;
+                    if ((rc = upload_plan(ctx, plan, dp))) return rc;
+                    HIPCHK(ctx, launch_init(dp.frames, 1, plan.max_M, (HypState *)ctx->hs.p, (PoseEval *)ctx->pose.p,
+                                            (int *)ctx->hlev.p, MODE_DIAG, frame->poses_in, l, ctx->stream));
+                    const LaunchGroup &g = plan.groups[0];
+                    PassArgs a;
+                    a.frames = dp.frames;
+                    a.items = dp.items + g.item_off;
+                    a.n_items = g.n_items;
+                    a.level = l;
+                    a.pose = (const PoseEval *)ctx->pose.p;
+                    a.hlev = (const int *)ctx->hlev.p;
+                    a.partials = (float *)ctx->partials.p;
+                    HIPCHK(ctx, launch_pass(L.C, L.dtype, g.tc, a, ctx->stream));   // warm-up
+                    hipEvent_t e0 = pool_event(ctx), e1 = pool_event(ctx);
+                    HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
+                    const int reps = 3;
+                    for (int r = 0; r < reps; ++r) HIPCHK(ctx, launch_pass(L.C, L.dtype, g.tc, a, ctx->stream));
+                    HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
+                    HIPCHK(ctx, hipEventSynchronize(e1));
+                    float ms = 0;
+                    HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
+                    ctx->event_pool.push_back(e0);
+                    ctx->event_pool.push_back(e1);
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = tc;
+                    }
+                }
+            }
+        }
+        ctx->tuned[key] = best;
+        if (!ctx->tune_cache.empty()) {
+            std::ofstream out(ctx->tune_cache, std::ios::app);
+            out << key << " " << best.G << " " << best.PPG << " " << best.grid << "\n";
+        }
+    }
+    return PILOT_OK;
+}
+
+int pilot_tile_choice(pilot_ctx *ctx, int C, int dtype, int N, int M, char *buf, int buflen)
+{
+    if (!ctx || !buf || buflen < 1) return fail(ctx, PILOT_EINVAL, "ctx/buf: invalid");
+    TileConfig tc = choose_tile(ctx, C, dtype, N, M);
+    snprintf(buf, buflen, "G=%d PPG=%d BPC=%d tuned=%d", tc.G, tc.PPG, tc.grid,
+             (int)ctx->tuned.count(tune_key(C, dtype, N, M)));
+    return PILOT_OK;
+}
+
+int pilot_get_stats(pilot_ctx *ctx, pilot_stats *out, int reset)
+{
+    if (!ctx || !out) return fail(ctx, PILOT_EINVAL, "ctx/out: NULL");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    int rc = collect_timings(ctx);
+    if (rc) return rc;
+    memset(out, 0, sizeof *out);
+    unsigned long long pairs[kStatClasses] = {0};
+    if (ctx->pairs.p) {
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        HIPCHK(ctx, hipMemcpy(pairs, ctx->pairs.p, sizeof pairs, hipMemcpyDeviceToHost));
+    }
+    static const int Cs[5] = {16, 32, 64, 128, 256};
+    for (int l = 0; l < PILOT_MAX_LEVELS; ++l)
+        for (int ci = 0; ci < 5; ++ci)
+            for (int dt = 0; dt < 2; ++dt) {
+                const int k = l * 10 + ci * 2 + dt;
+                out->pairs[l] += pairs[k];
+                out->pair_bytes[l] += pairs[k] * 4ull * Cs[ci] * elem_size(dt);
+                out->launches[l] += ctx->launches[k];
+                out->pass_ms[l] += ctx->pass_ms[k];
+                out->timed_launches[l] += ctx->timed_launches[k];
+            }
+    out->graph_replays = ctx->graph_replays;
+    out->graph_captures = ctx->graph_captures;
+    if (reset) {
+        if (ctx->pairs.p) HIPCHK(ctx, hipMemset(ctx->pairs.p, 0, kStatClasses * sizeof(unsigned long long)));
+        memset(ctx->pass_ms, 0, sizeof ctx->pass_ms);
+        memset(ctx->timed_launches, 0, sizeof ctx->timed_launches);
+        memset(ctx->launches, 0, sizeof ctx->launches);
+        ctx->graph_replays = ctx->graph_captures = 0;
+    }
+    return PILOT_OK;
+}
+
+// Serving entry points are provided by pilot_serving.cpp.
+
+}  // extern "C"

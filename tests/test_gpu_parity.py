@@ -1,0 +1,144 @@
+"""GPU path (libpilot, through the C ABI) against the FP64 oracle, element by
+element on the same seeded inputs."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import frames as S
+from tests.gpu_common import (BF16_TOL_DEG, BF16_TOL_M, NEQ_TOL, POSE_TOL_DEG, POSE_TOL_M, bf16_copy,
+                              border_count, check_best, compare_solutions, mask_edges, rel_frobenius, say,
+                              unpack_h21)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2606_31098_amd.pilot import Context
+    return Context(0)
+
+
+def solve_gpu(ctx, frame, dtype="f32"):
+    from paper_2606_31098_amd.pilot import DeviceFrame
+    df = DeviceFrame(frame, dtype=dtype)
+    r = ctx.solve([df])[0]
+    torch.cuda.synchronize()
+    return r.numpy()
+
+
+def pyramid_frame(seed=1, N=1000, M=13, iters=(6, 6, 6), levels=((30, 40, 16), (60, 80, 32), (120, 160, 64)),
+                  noise=True):
+    return S.make_frame(2, 0, noise=noise, N=N, M=M, level_shapes=levels, iters=iters, dsm_side=128, seed=seed)
+
+
+# --------------------------------------------------------------------------- normal equations
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_normal_equations_match_oracle(ctx, dtype):
+    from paper_2606_31098_amd.pilot import DeviceFrame
+    f = pyramid_frame(seed=3, N=1500, M=11)
+    rng = np.random.default_rng(0)
+    poses = np.stack([oracle.compose(oracle.se3_exp(np.concatenate([rng.normal(0, 2, 3), rng.normal(0, 0.02, 3)])),
+                                     f.gt_pose) for _ in range(f.M)])
+    mask_edges(f, poses)
+    if dtype == "bf16":
+        f = bf16_copy(f)
+    df = DeviceFrame(f, dtype=dtype)
+    of = oracle.OracleFrame(f)
+    for lvl in range(len(f.levels)):
+        say(f"linearize dtype={dtype} level={lvl} C={f.levels[lvl].C} N={f.levels[lvl].N} M={f.M}")
+        H21, g, cost, n = ctx.linearize(df, lvl, torch.as_tensor(poses, device="cuda"))
+        torch.cuda.synchronize()
+        H = unpack_h21(H21.cpu().numpy())
+        g, cost, n = g.cpu().numpy(), cost.cpu().numpy(), n.cpu().numpy()
+        for m in range(f.M):
+            Ho, go, co, no = oracle.linearize(of, lvl, poses[m])
+            err = rel_frobenius(np.concatenate([H[m], g[m][:, None]], 1), np.concatenate([Ho, go[:, None]], 1))
+            assert err <= NEQ_TOL, (lvl, m, err)
+            assert abs(cost[m] - co) <= 1e-5 * abs(co), (lvl, m, cost[m], co)
+            assert abs(int(n[m]) - no) <= border_count(f.levels[lvl], poses[m]), (lvl, m, n[m], no)
+
+
+# --------------------------------------------------------------------------- full solves
+def test_single_hypothesis_solve_matches_oracle(ctx):
+    f = S.make_frame(1, 0)                      # 1 frame, 1 hypothesis, N=1024, 120x160x32, 20 iterations
+    say("solve config-1 frame")
+    gpu = solve_gpu(ctx, f)
+    orc = oracle.solve(f, threads=8)
+    rows, fails = compare_solutions(f, gpu, orc, POSE_TOL_M, POSE_TOL_DEG, "cfg1")
+    say(rows)
+    assert not fails, fails
+    assert gpu["status"][0] == orc["status"][0]
+    assert abs(gpu["cost"][0] - orc["cost"][0]) <= 1e-5 * abs(orc["cost"][0])
+    assert gpu["best"] == orc["best"] == 0
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_multi_hypothesis_pyramid_matches_oracle(ctx, seed):
+    f = pyramid_frame(seed=seed)
+    say(f"solve pyramid seed={seed} N=1000 M=13")
+    gpu = solve_gpu(ctx, f)
+    orc = oracle.solve(f, threads=8)
+    rows, fails = compare_solutions(f, gpu, orc, POSE_TOL_M, POSE_TOL_DEG, f"seed{seed}")
+    for r in rows:
+        say(r)
+    assert not fails, fails
+    assert check_best(f, gpu, orc, POSE_TOL_M, POSE_TOL_DEG)
+    assert np.all(gpu["iterations"] <= sum(L.iters for L in f.levels))
+
+
+def test_bf16_solve_matches_oracle_on_rounded_inputs(ctx):
+    f = pyramid_frame(seed=4)
+    fb = bf16_copy(f)
+    say("solve bf16 pyramid")
+    gpu = solve_gpu(ctx, f, dtype="bf16")
+    orc_b = oracle.solve(fb, threads=8)        # same (rounded) inputs: FP32-arithmetic tolerance
+    rows, fails = compare_solutions(f, gpu, orc_b, POSE_TOL_M, POSE_TOL_DEG, "bf16-vs-rounded")
+    assert not fails, fails
+    orc = oracle.solve(f, threads=8)           # unrounded inputs: the bf16 accuracy bar
+    rows, fails = compare_solutions(f, gpu, orc, BF16_TOL_M, BF16_TOL_DEG, "bf16-vs-f32")
+    for r in rows:
+        say(r)
+    assert not fails, fails
+
+
+def test_noise_free_frame_converges_to_ground_truth(ctx):
+    f = S.make_frame(1, 0, noise=False)
+    say("solve noise-free config-1 frame")
+    gpu = solve_gpu(ctx, f)
+    te, re = S.pose_errors(gpu["poses"], f.gt_pose)
+    assert te[0] < 1e-3 and re[0] < 1e-4
+    assert gpu["status"][0] == 0
+
+
+# --------------------------------------------------------------------------- edge cases
+def test_degenerate_hypotheses(ctx):
+    f = pyramid_frame(seed=5, N=300, M=5, iters=(3, 3, 3))
+    P = f.poses.copy()
+    P[1, 0] = np.nan                                   # non-finite input pose
+    P[2, 9:] = [0.0, 0.0, -1e5]                        # everything behind the camera
+    f.poses = P
+    say("solve degenerate cases")
+    gpu = solve_gpu(ctx, f)
+    orc = oracle.solve(f, threads=4)
+    assert gpu["status"][1] == 3 and orc["status"][1] == 3
+    assert gpu["status"][2] == 3 and orc["status"][2] == 3
+    assert gpu["best"] not in (1, 2)
+    rows, fails = compare_solutions(f, gpu, orc, POSE_TOL_M, POSE_TOL_DEG, "degenerate")
+    assert not [x for x in fails if x[1] not in (1, 2)]
+
+
+def test_empty_anchor_level_and_zero_iterations(ctx):
+    f = pyramid_frame(seed=6, N=200, M=3, iters=(0, 4, 4))
+    f.lm["min_valid"] = 0
+    L = f.levels[1]
+    L.x, L.y, L.z = L.x[:0], L.y[:0], L.z[:0]
+    L.ref = L.ref[:0]
+    say("solve with an empty level")
+    gpu = solve_gpu(ctx, f)
+    orc = oracle.solve(f, threads=4)
+    rows, fails = compare_solutions(f, gpu, orc, POSE_TOL_M, POSE_TOL_DEG, "empty")
+    assert not fails, fails
+    assert np.all(gpu["status"] == orc["status"])

@@ -256,6 +256,19 @@ def test_dsm_lookup_against_raster():
     assert h == pytest.approx(float(D.heights[3, 0])) and hx == 0.0
 
 
+def test_non_finite_pose_is_degenerate_not_a_crash():
+    f = small_frame(M=3)
+    P = f.poses.copy()
+    P[1, 0] = np.nan
+    P[2, 9:] = [0.0, 0.0, -1e5]
+    f.poses = P
+    of = oracle.OracleFrame(f)
+    assert math.isnan(oracle.dsm(of, float("nan"), 0.0)[0]) is False
+    r = oracle.solve(f, threads=2)
+    assert r["status"][1] == oracle.DEGENERATE and r["status"][2] == oracle.DEGENERATE
+    assert r["best"] == 0
+
+
 # ---------------------------------------------------------------- normal equations
 def total_cost(of, l, T):
     return oracle.linearize(of, l, T)[2]
