@@ -40,6 +40,8 @@ def parse():
     p.add_argument("--cpu-hyps", type=int, default=48, help="hypotheses in the oracle sample")
     p.add_argument("--no-bf16", action="store_true")
     p.add_argument("--frame-seed", type=int, default=0)
+    p.add_argument("--no-tune", action="store_true", help="heuristic tiles instead of the autotuner")
+    p.add_argument("--tune-cache", default=None, help="autotune cache file (read, and appended when tuning)")
     return p.parse_args()
 
 
@@ -110,7 +112,15 @@ def main():
     torch.cuda.synchronize()
 
     # ---------------------------------------------------------------- timed region (graph replays)
-    ctx = Context(0)
+    tune_flag = 0 if args.no_tune else A.FLAG_AUTOTUNE
+    ctx = Context(0, flags=tune_flag, tune_cache=args.tune_cache)
+    t_tune = time.perf_counter()
+    if tune_flag:
+        ctx.autotune(df)                       # tile choice per level, timed on this frame (untimed here)
+        torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t_tune
+    tiles = [ctx.tile_choice(L.C, A.F32, L.N, df.M) for L in frame.levels]
+    print(f"# tiles ({tune_s:.1f}s): {tiles}", file=sys.stderr, flush=True)
     wall, lat, st, res = timed_solves(ctx, df, args.steps, args.warmup)
     pairs = sum(st.pairs)
     ms_per_step = wall * 1e3 / args.steps
@@ -122,7 +132,9 @@ def main():
           f"best={out['best']} err={te[0]:.3f} m {re_[0]:.4f} deg", file=sys.stderr, flush=True)
 
     # ---------------------------------------------------------------- roofline: per-launch events
-    pctx = Context(0, flags=A.FLAG_PROFILE)
+    pctx = Context(0, flags=A.FLAG_PROFILE | tune_flag, tune_cache=args.tune_cache)
+    if tune_flag:
+        pctx.autotune(df)
     pwall, plat, pst, _ = timed_solves(pctx, df, max(3, args.steps // 4), 1)
     fine = max(l for l in range(A.MAX_LEVELS) if pst.timed_launches[l] > 0)
     n_launch = pst.timed_launches[fine]
@@ -153,15 +165,19 @@ def main():
     bf16 = None
     if not args.no_bf16:
         dfb = DeviceFrame(frame, dtype="bf16")
-        bctx = Context(0)
+        bctx = Context(0, flags=tune_flag, tune_cache=args.tune_cache)
+        if tune_flag:
+            bctx.autotune(dfb)
         bwall, blat, bst, bres = timed_solves(bctx, dfb, args.steps, args.warmup)
         bout = bres.numpy()
         bte, bre = S.pose_errors(bout["poses"][bout["best"]], frame.gt_pose)
         bf16 = {"value": sum(bst.pairs) / bwall, "ms_per_step": bwall * 1e3 / args.steps,
                 "latency_ms": {"p50": percentile(blat, 50), "p99": percentile(blat, 99)},
-                "speedup_vs_f32": (sum(bst.pairs) / bwall) / evals_per_s,
+                "evals_per_step": sum(bst.pairs) / args.steps,
+                "solve_speedup_vs_f32": ms_per_step / (bwall * 1e3 / args.steps),
                 "best_pose_error_m": float(bte[0]), "best_pose_error_deg": float(bre[0])}
-        print(f"# bf16: {bf16['ms_per_step']:.3f} ms/step ({bf16['speedup_vs_f32']:.2f}x)", file=sys.stderr, flush=True)
+        print(f"# bf16: {bf16['ms_per_step']:.3f} ms/step ({bf16['solve_speedup_vs_f32']:.2f}x per solve)",
+              file=sys.stderr, flush=True)
         bctx.close()
 
     # ---------------------------------------------------------------- CPU baseline (oracle sample)
@@ -200,6 +216,7 @@ def main():
         "gb_per_s_algorithmic": gbs,
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
         "evals_per_step": pairs / args.steps,
+        "tiles": tiles,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "bf16_same_workload": bf16,

@@ -53,16 +53,35 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpilogueArgs e)
         const int hh = t / kNV, v = t - hh * kNV;
         const float *src = e.partials + (size_t)ti.first_item * stride + t;
         double s = 0.0;
+        // four interleaved accumulators (fixed order) keep four loads in flight
+        const int n = ti.n_ptiles;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         if (v < kNSum) {
-            for (int it = 0; it < ti.n_ptiles; ++it) s += (double)src[(size_t)it * stride];
+            int it = 0;
+            for (; it + 4 <= n; it += 4) {
+                s0 += (double)src[(size_t)it * stride];
+                s1 += (double)src[(size_t)(it + 1) * stride];
+                s2 += (double)src[(size_t)(it + 2) * stride];
+                s3 += (double)src[(size_t)(it + 3) * stride];
+            }
+            for (; it < n; ++it) s0 += (double)src[(size_t)it * stride];
         } else if (v == kCostSlot) {
-            for (int it = 0; it < ti.n_ptiles; ++it) {
+            auto cost_at = [&](int it) {
                 const float *q = src + (size_t)it * stride;
                 const unsigned long long bits = (unsigned long long)__float_as_uint(q[0]) |
                                                 ((unsigned long long)__float_as_uint(q[1]) << 32);
-                s += __longlong_as_double((long long)bits);
+                return __longlong_as_double((long long)bits);
+            };
+            int it = 0;
+            for (; it + 4 <= n; it += 4) {
+                s0 += cost_at(it);
+                s1 += cost_at(it + 1);
+                s2 += cost_at(it + 2);
+                s3 += cost_at(it + 3);
             }
+            for (; it < n; ++it) s0 += cost_at(it);
         }
+        s = (s0 + s1) + (s2 + s3);
         s_sum[hh][v] = s;
     }
     __syncthreads();
