@@ -85,7 +85,8 @@ typedef struct {
     int32_t device;             /* HIP device ordinal                                   */
     int32_t flags;              /* PILOT_FLAG_*                                         */
     void *stream;               /* hipStream_t for all work; NULL = null stream         */
-    size_t hbm_budget_bytes;    /* cap on workspace + admitted serving frames; 0 = none */
+    size_t hbm_budget_bytes;    /* pilot_solve: cap on workspace; serving: cap on the  */
+                                /* summed pilot_admit_cost of admitted frames; 0 = none */
     const char *tune_cache;     /* autotune cache file (read at create, appended); NULL */
     int32_t max_slots;          /* serving slots; 0 = 64                                */
     int32_t reserved;
@@ -134,6 +135,17 @@ typedef struct {
     double step_tol_t, step_tol_r, z_min;
     int32_t min_valid;          /* fewer visible anchors at a level start: DEGENERATE */
     int32_t reserved;
+    /* Optional hypothesis generation on the device (supplement "Multi-Hypothesis
+     * Refinement": hypotheses around the propagated prior in (x, y, yaw)).
+     * When hyp_offsets is non-NULL, poses_in is ignored and hypothesis m is the
+     * prior pose shifted by (dx, dy) metres in world x, y and rotated by dyaw
+     * about the world z axis through its camera centre.  The prior is row
+     * prior_best[0] of prior_poses (row 0 if prior_best is NULL or holds -1),
+     * so a frame can start from the previous frame's result without a host
+     * round trip. */
+    const double *prior_poses;  /* device, rows of 12                              */
+    const int32_t *prior_best;  /* device, 1 index, or NULL                         */
+    const double *hyp_offsets;  /* device, M*3: dx, dy, dyaw                        */
 } pilot_frame;
 
 /* Caller-owned device buffers. */
@@ -194,19 +206,25 @@ int pilot_linearize(pilot_ctx *ctx, const pilot_frame *frame, int level,
 int pilot_admit_cost(pilot_ctx *ctx, const pilot_frame *frame, size_t *bytes);
 
 /* Admit a frame.  PILOT_EAGAIN (nothing enqueued) when no slot is free or
- * the budget would be exceeded.  Hypotheses come from frame->poses_in,
- * copied on the stream at admission (the caller may reuse that buffer after
- * its stream passes this call). */
+ * the budget would be exceeded.  Hypotheses (poses_in, or generated from the
+ * prior) are read on the stream at admission; the frame's other inputs must
+ * stay valid until pilot_poll reports the slot finished.  A context with
+ * active slots accepts no pilot_solve / pilot_linearize. */
 int pilot_admit(pilot_ctx *ctx, const pilot_frame *frame, const pilot_result *result,
                 int *slot);
 
-/* One LM pass for every active slot (enqueued on the stream). */
+/* One LM pass for every active slot (enqueued on the stream), followed by
+ * the result write-out of slots that finished.  At most two steps are in
+ * flight: a third call first waits for the oldest. */
 int pilot_step(pilot_ctx *ctx);
 
-/* 1 if the slot's frame has finished and its results are written (the slot
- * is then free), 0 if still running, negative on error.  Reads a small
- * device flag: synchronises with the work enqueued before it. */
+/* 1 if a completed step has seen the slot's frame finish (its results are
+ * then written and the slot is free for reuse), 0 if not yet, negative on
+ * error.  Does not block. */
 int pilot_poll(pilot_ctx *ctx, int slot);
+
+/* Block until every enqueued step has completed. */
+int pilot_sync(pilot_ctx *ctx);
 
 /* Number of active slots and budget bytes in use. */
 int pilot_serving_state(pilot_ctx *ctx, int *active_slots, size_t *bytes_in_use);

@@ -251,8 +251,7 @@ def solve(frame, hyps=None, threads=None, trace=False, of: OracleFrame = None):
     rows = sum(int(L.iters) for L in frame.levels)
     tr = np.zeros((k, max(rows, 1), 4)) if trace else None
     L = lib()
-    if threads is not None:
-        L.orc_set_threads(int(threads))
+    L.orc_set_threads(int(threads) if threads else 0)          # 0: all OpenMP threads
     L.orc_solve(of.ptr, _p(sub), 0, k, _p(out), _p(cost), its.ctypes.data_as(_ip),
                 st.ctypes.data_as(_ip), _p(tr) if trace else _dp(), max(rows, 1))
     b = L.orc_best(_p(cost), st.ctypes.data_as(_ip), k)

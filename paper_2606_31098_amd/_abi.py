@@ -49,7 +49,8 @@ class Frame(C.Structure):
                 ("tau", C.c_double), ("lambda_up", C.c_double), ("lambda_down", C.c_double),
                 ("lambda_min_rel", C.c_double), ("lambda_max_rel", C.c_double),
                 ("step_tol_t", C.c_double), ("step_tol_r", C.c_double), ("z_min", C.c_double),
-                ("min_valid", C.c_int32), ("reserved", C.c_int32)]
+                ("min_valid", C.c_int32), ("reserved", C.c_int32),
+                ("prior_poses", _dp), ("prior_best", _vp), ("hyp_offsets", _dp)]
 
 
 class Result(C.Structure):
@@ -65,7 +66,8 @@ class Stats(C.Structure):
 
 EXPORTS = ["pilot_create", "pilot_destroy", "pilot_last_error", "pilot_solve", "pilot_linearize",
            "pilot_admit_cost", "pilot_admit", "pilot_step", "pilot_poll", "pilot_serving_state",
-           "pilot_get_stats", "pilot_autotune", "pilot_tile_choice", "pilot_abi_version", "pilot_sizeof"]
+           "pilot_get_stats", "pilot_autotune", "pilot_tile_choice", "pilot_abi_version", "pilot_sizeof",
+           "pilot_sync"]
 
 _lib = None
 
@@ -92,6 +94,7 @@ def load(path: str = LIB_PATH):
     L.pilot_step.argtypes = [_vp]
     L.pilot_poll.argtypes = [_vp, C.c_int]
     L.pilot_serving_state.argtypes = [_vp, P(C.c_int), P(C.c_size_t)]
+    L.pilot_sync.argtypes = [_vp]
     L.pilot_get_stats.argtypes = [_vp, P(Stats), C.c_int]
     L.pilot_autotune.argtypes = [_vp, P(Frame)]
     L.pilot_tile_choice.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_char_p, C.c_int]

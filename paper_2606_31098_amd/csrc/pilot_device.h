@@ -25,8 +25,8 @@ struct LevelDev {
     double fx, fy, cx, cy;
     int H, W, C, N;
     int iters, loss_kind;
-    float loss_b;
-    int dtype;
+    double loss_b;
+    int dtype, pad;
 };
 
 // One frame (solve) or one serving slot.
@@ -46,9 +46,12 @@ struct FrameDev {
     double dsm_x0, dsm_y0, dsm_gsd;
     // LM control
     double tau, up, down, lmin_rel, lmax_rel, tol_t, tol_r;
-    float z_min;
-    int min_valid;
+    double z_min;
+    int min_valid, pad2;
     const double *poses_in;
+    const double *prior_poses;   // device hypothesis generation (hyp_offsets non-NULL)
+    const int *prior_best;
+    const double *hyp_offsets;
     // outputs
     double *poses_out, *cost_out;
     int *iters_out, *status_out, *best_out;

@@ -131,7 +131,31 @@ __global__ __launch_bounds__(256) void init_kernel(const FrameDev *frames, HypSt
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= f.M) return;
     const int gh = f.hyp_base + m;
-    const double *src = (mode == MODE_DIAG) ? dposes + (size_t)12 * m : f.poses_in + (size_t)12 * m;
+    double src[12];
+    if (mode == MODE_DIAG) {
+        for (int i = 0; i < 12; ++i) src[i] = dposes[(size_t)12 * m + i];
+    } else if (f.hyp_offsets) {
+        // hypothesis m around the prior: centre += (dx, dy, 0), R_wc <- Rz(dyaw) R_wc,
+        // i.e. R <- R Rz(-dyaw), t <- -R C
+        const int b = f.prior_best ? max(*f.prior_best, 0) : 0;
+        const double *T = f.prior_poses + (size_t)12 * b;
+        const double dx = f.hyp_offsets[3 * m], dy = f.hyp_offsets[3 * m + 1], dz = f.hyp_offsets[3 * m + 2];
+        double Cw[3];
+        for (int i = 0; i < 3; ++i) Cw[i] = -(T[i] * T[9] + T[3 + i] * T[10] + T[6 + i] * T[11]);   // -R^T t
+        Cw[0] += dx;
+        Cw[1] += dy;
+        double sz, cz;
+        sincos(dz, &sz, &cz);
+        for (int r = 0; r < 3; ++r) {
+            const double a0 = T[3 * r], a1 = T[3 * r + 1];
+            src[3 * r] = a0 * cz + a1 * sz;           // R Rz(-dyaw): columns 0, 1 rotate
+            src[3 * r + 1] = -a0 * sz + a1 * cz;
+            src[3 * r + 2] = T[3 * r + 2];
+        }
+        for (int r = 0; r < 3; ++r) src[9 + r] = -(src[3 * r] * Cw[0] + src[3 * r + 1] * Cw[1] + src[3 * r + 2] * Cw[2]);
+    } else {
+        for (int i = 0; i < 12; ++i) src[i] = f.poses_in[(size_t)12 * m + i];
+    }
     HypState s;
     bool finite = true;
 #pragma unroll
@@ -180,6 +204,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const FrameDev *frames, c
                                                         const int *hlev)
 {
     const FrameDev &f = frames[blockIdx.x];
+    if (f.M <= 0) return;                          // unused serving slot
     __shared__ double s_cost[256];
     __shared__ int s_idx[256];
     __shared__ int s_skip;

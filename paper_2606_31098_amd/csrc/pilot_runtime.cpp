@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -68,7 +69,16 @@ struct TimedLaunch {
     int level, cls;
 };
 
-struct ServingSlot;
+struct ServingSlot {
+    bool active = false;
+    int M = 0;
+    int hyp_base = 0;
+    size_t bytes = 0;
+    uint64_t admit_step = 0;
+    pilot_frame frame;
+};
+
+constexpr int kFlagRing = 4;
 
 }  // namespace
 
@@ -106,6 +116,28 @@ struct pilot_ctx {
     uint64_t timed_launches[kStatClasses] = {0};
     uint64_t launches[kStatClasses] = {0};
     uint64_t graph_replays = 0, graph_captures = 0;
+
+    // serving
+    std::vector<ServingSlot> slots;
+    DevBuf s_frames, s_desc, s_done;
+    int arena_cap = 0;                          // hypotheses in the slot arena
+    std::vector<std::pair<int, int>> arena_free;   // (offset, length), sorted
+    size_t serv_bytes = 0;
+    bool serv_dirty = true;
+    Plan serv_plan;                             // work lists over the active slots
+    uint64_t steps_enqueued = 0;
+    struct FlagBuf {
+        int *host = nullptr;
+        hipEvent_t ev = nullptr;
+        uint64_t step = 0;
+        bool used = false;
+    } flagbuf[kFlagRing];
+    int n_active() const
+    {
+        int n = 0;
+        for (const ServingSlot &x : slots) n += x.active ? 1 : 0;
+        return n;
+    }
 };
 
 namespace {
@@ -148,7 +180,8 @@ int validate_frame(pilot_ctx *ctx, const pilot_frame *f, int fi, bool need_poses
     if (f->n_levels < 1 || f->n_levels > PILOT_MAX_LEVELS)
         return fail(ctx, PILOT_EINVAL, "frames[%d].n_levels: must be 1..%d (got %d)", fi, PILOT_MAX_LEVELS, f->n_levels);
     if (f->M < 1 || f->M > 65536) return fail(ctx, PILOT_EINVAL, "frames[%d].M: must be 1..65536 (got %d)", fi, f->M);
-    if (need_poses && !f->poses_in) return fail(ctx, PILOT_EINVAL, "frames[%d].poses_in: NULL", fi);
+    if (need_poses && !f->poses_in && !(f->hyp_offsets && f->prior_poses))
+        return fail(ctx, PILOT_EINVAL, "frames[%d].poses_in: NULL (and no prior_poses + hyp_offsets)", fi);
     for (int l = 0; l < f->n_levels; ++l) {
         const pilot_level &L = f->level[l];
         if (L.H < 2 || L.W < 2)
@@ -216,13 +249,16 @@ int validate_frame(pilot_ctx *ctx, const pilot_frame *f, int fi, bool need_poses
 }
 
 // ---------------------------------------------------------------- workspace
-int ensure(pilot_ctx *ctx, DevBuf &b, size_t bytes, bool zero = false)
+// Grow a workspace buffer.  Solve workspace is charged against the HBM
+// budget; serving buffers (check_budget = false) are covered by the
+// per-frame admission costs instead.
+int ensure(pilot_ctx *ctx, DevBuf &b, size_t bytes, bool zero = false, bool check_budget = true)
 {
     if (bytes <= b.cap) return PILOT_OK;
     size_t want = std::max(bytes, b.cap + b.cap / 2);
     want = (want + 4095) & ~(size_t)4095;
     size_t total = ctx->ws_bytes - b.cap + want;
-    if (ctx->budget && total > ctx->budget) {
+    if (check_budget && ctx->budget && total > ctx->budget) {
         want = bytes;
         total = ctx->ws_bytes - b.cap + want;
         if (total > ctx->budget)
@@ -343,7 +379,7 @@ void fill_frame_dev(FrameDev &d, const pilot_frame &f, const pilot_result *r, in
         o.N = L.N;
         o.iters = L.iters;
         o.loss_kind = L.loss_kind;
-        o.loss_b = (float)L.loss_scale;
+        o.loss_b = L.loss_scale;
         o.dtype = L.dtype;
     }
     d.n_levels = f.n_levels;
@@ -381,9 +417,12 @@ void fill_frame_dev(FrameDev &d, const pilot_frame &f, const pilot_result *r, in
     d.lmax_rel = f.lambda_max_rel;
     d.tol_t = f.step_tol_t;
     d.tol_r = f.step_tol_r;
-    d.z_min = (float)f.z_min;
+    d.z_min = f.z_min;
     d.min_valid = f.min_valid;
     d.poses_in = f.poses_in;
+    d.prior_poses = f.prior_poses;
+    d.prior_best = f.prior_best;
+    d.hyp_offsets = f.hyp_offsets;
     if (r) {
         d.poses_out = r->poses_out;
         d.cost_out = r->cost;
@@ -411,22 +450,24 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
     key << "n" << n << "_h" << base << "_m" << plan.max_M;
     for (int l = 0; l < plan.max_levels; ++l) {
         if (only_level >= 0 && l != only_level) continue;
-        std::map<std::pair<int, int>, std::vector<int>> by_class;
+        // each frame's tiles depend on its own shape only, so its sums (and
+        // results) are the same alone or batched with any other frames
+        std::map<std::array<int, 4>, std::vector<int>> by_class;
         for (int i = 0; i < n; ++i)
-            if (l < frames[i].n_levels) by_class[{frames[i].level[l].C, frames[i].level[l].dtype}].push_back(i);
+            if (l < frames[i].n_levels) {
+                const pilot_level &L = frames[i].level[l];
+                const TileConfig tc = choose_tile(ctx, L.C, L.dtype, L.N, frames[i].M);
+                by_class[{L.C, L.dtype, tc.G, tc.PPG}].push_back(i);
+            }
         for (auto &kv : by_class) {
             LaunchGroup g;
             g.level = l;
-            g.C = kv.first.first;
-            g.dtype = kv.first.second;
-            // one tile shape per group, chosen for its largest frame
-            int Nmax = 0, Mmax = 0, iters = 0;
-            for (int i : kv.second) {
-                Nmax = std::max(Nmax, frames[i].level[l].N);
-                Mmax = std::max(Mmax, frames[i].M);
-                iters = std::max(iters, frames[i].level[l].iters);
-            }
-            g.tc = choose_tile(ctx, g.C, g.dtype, Nmax, Mmax);
+            g.C = kv.first[0];
+            g.dtype = kv.first[1];
+            int iters = 0;
+            for (int i : kv.second) iters = std::max(iters, frames[i].level[l].iters);
+            const pilot_level &L0 = frames[kv.second[0]].level[l];
+            g.tc = choose_tile(ctx, g.C, g.dtype, L0.N, frames[kv.second[0]].M);
             g.item_off = (int)plan.items.size();
             g.tile_off = (int)plan.tiles.size();
             for (int i : kv.second) {
@@ -673,8 +714,13 @@ void pilot_destroy(pilot_ctx *ctx)
         if (s.ev) hipEventSynchronize(s.ev), hipEventDestroy(s.ev);
         if (s.p) hipHostFree(s.p);
     }
-    for (DevBuf *b : {&ctx->desc, &ctx->hs, &ctx->pose, &ctx->hlev, &ctx->partials, &ctx->pairs})
+    for (DevBuf *b : {&ctx->desc, &ctx->hs, &ctx->pose, &ctx->hlev, &ctx->partials, &ctx->pairs,
+                      &ctx->s_frames, &ctx->s_desc, &ctx->s_done})
         if (b->p) hipFree(b->p);
+    for (auto &fb : ctx->flagbuf) {
+        if (fb.ev) hipEventDestroy(fb.ev);
+        if (fb.host) hipHostFree(fb.host);
+    }
     if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     delete ctx;
 }
@@ -696,6 +742,7 @@ int pilot_solve(pilot_ctx *ctx, const pilot_frame *frames, int n_frames, const p
         total += frames[i].M;
     }
     if (total > (1L << 24)) return fail(ctx, PILOT_EINVAL, "total hypotheses %ld exceed 2^24", total);
+    if (ctx->n_active() > 0) return fail(ctx, PILOT_EINVAL, "context has active serving slots");
     HIPCHK(ctx, hipSetDevice(ctx->device));
 
     if (ctx->flags & PILOT_FLAG_AUTOTUNE) {
@@ -762,6 +809,7 @@ int pilot_linearize(pilot_ctx *ctx, const pilot_frame *frame, int level, const d
         return fail(ctx, PILOT_EINVAL, "level: must be 0..%d (got %d)", frame->n_levels - 1, level);
     if (!poses) return fail(ctx, PILOT_EINVAL, "poses: NULL");
     if (!H21 || !g6 || !cost || !nvalid) return fail(ctx, PILOT_EINVAL, "H21/g6/cost/nvalid: NULL");
+    if (ctx->n_active() > 0) return fail(ctx, PILOT_EINVAL, "context has active serving slots");
     HIPCHK(ctx, hipSetDevice(ctx->device));
     Plan plan;
     build_plan(ctx, frame, 1, nullptr, level, plan);
@@ -786,6 +834,7 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
     if (!ctx) return fail(nullptr, PILOT_EINVAL, "ctx: NULL");
     int rc = validate_frame(ctx, frame, 0, true);
     if (rc) return rc;
+    if (ctx->n_active() > 0) return fail(ctx, PILOT_EINVAL, "context has active serving slots");
     HIPCHK(ctx, hipSetDevice(ctx->device));
     for (int l = 0; l < frame->n_levels; ++l) {
         const pilot_level &L = frame->level[l];
@@ -886,6 +935,294 @@ int pilot_get_stats(pilot_ctx *ctx, pilot_stats *out, int reset)
     return PILOT_OK;
 }
 
-// Serving entry points are provided by pilot_serving.cpp.
+// ================================================================ serving
+}  // extern "C"
+
+namespace {
+
+size_t per_hyp_bytes() { return sizeof(HypState) + sizeof(PoseEval) + sizeof(int); }
+
+// Input bytes a frame declares (maps, anchors, descriptors) plus its
+// hypothesis state and the largest partial-sum block of its levels.
+size_t frame_cost(const pilot_ctx *ctx, const pilot_frame &f)
+{
+    size_t in = (size_t)f.M * 12 * sizeof(double);
+    size_t part = 0;
+    for (int l = 0; l < f.n_levels; ++l) {
+        const pilot_level &L = f.level[l];
+        const size_t es = elem_size(L.dtype);
+        in += (size_t)L.H * L.W * L.C * es + (size_t)L.N * (3 * sizeof(float) + L.C * es);
+        if (L.qconf) in += (size_t)L.H * L.W * sizeof(float);
+        if (L.ref_w) in += (size_t)L.N * sizeof(float);
+        const TileConfig tc = choose_tile(ctx, L.C, L.dtype, L.N, f.M);
+        const size_t items = (size_t)((f.M + tc.G - 1) / tc.G) * n_ptiles_of(tc, L.N);
+        part = std::max(part, items * tc.G * kNV * sizeof(float));
+    }
+    if (f.use_range) in += (size_t)f.Hd * f.Wd * sizeof(float);
+    return in + (size_t)f.M * per_hyp_bytes() + part;
+}
+
+int arena_alloc(pilot_ctx *ctx, int M)
+{
+    for (size_t i = 0; i < ctx->arena_free.size(); ++i) {
+        auto &blk = ctx->arena_free[i];
+        if (blk.second >= M) {
+            const int off = blk.first;
+            blk.first += M;
+            blk.second -= M;
+            if (blk.second == 0) ctx->arena_free.erase(ctx->arena_free.begin() + i);
+            return off;
+        }
+    }
+    return -1;
+}
+
+void arena_release(pilot_ctx *ctx, int off, int M)
+{
+    auto &fl = ctx->arena_free;
+    fl.push_back({off, M});
+    std::sort(fl.begin(), fl.end());
+    std::vector<std::pair<int, int>> merged;
+    for (auto &b : fl) {
+        if (!merged.empty() && merged.back().first + merged.back().second == b.first)
+            merged.back().second += b.second;
+        else
+            merged.push_back(b);
+    }
+    fl.swap(merged);
+}
+
+int serving_init(pilot_ctx *ctx)
+{
+    if (!ctx->slots.empty()) return PILOT_OK;
+    int rc;
+    ctx->arena_cap = std::max(16384, ctx->max_slots * 512);
+    const size_t H = ctx->arena_cap;
+    if ((rc = ensure(ctx, ctx->hs, H * sizeof(HypState), false, false))) return rc;
+    if ((rc = ensure(ctx, ctx->pose, H * sizeof(PoseEval), false, false))) return rc;
+    if ((rc = ensure(ctx, ctx->hlev, H * sizeof(int), false, false))) return rc;
+    if ((rc = ensure(ctx, ctx->pairs, kStatClasses * sizeof(unsigned long long), true, false))) return rc;
+    if ((rc = ensure(ctx, ctx->s_frames, (size_t)ctx->max_slots * sizeof(FrameDev), true, false))) return rc;
+    if ((rc = ensure(ctx, ctx->s_done, (size_t)ctx->max_slots * sizeof(int), true, false))) return rc;
+    for (auto &fb : ctx->flagbuf) {
+        HIPCHK(ctx, hipHostMalloc((void **)&fb.host, (size_t)ctx->max_slots * sizeof(int), hipHostMallocDefault));
+        memset(fb.host, 0, (size_t)ctx->max_slots * sizeof(int));
+        HIPCHK(ctx, hipEventCreateWithFlags(&fb.ev, hipEventDisableTiming));
+    }
+    ctx->arena_free.assign(1, {0, ctx->arena_cap});
+    ctx->slots.assign(ctx->max_slots, ServingSlot());
+    return PILOT_OK;
+}
+
+// Work lists over the active slots: per level, slots grouped by (C, dtype).
+int serving_rebuild(pilot_ctx *ctx)
+{
+    Plan &plan = ctx->serv_plan;
+    plan = Plan();
+    std::vector<pilot_frame> frames;
+    std::vector<int> slot_of;
+    for (int i = 0; i < (int)ctx->slots.size(); ++i)
+        if (ctx->slots[i].active) {
+            frames.push_back(ctx->slots[i].frame);
+            slot_of.push_back(i);
+        }
+    for (int l = 0; l < PILOT_MAX_LEVELS; ++l) {
+        std::map<std::array<int, 4>, std::vector<int>> by_class;
+        for (int k = 0; k < (int)frames.size(); ++k)
+            if (l < frames[k].n_levels) {
+                const pilot_level &L = frames[k].level[l];
+                const TileConfig tc = choose_tile(ctx, L.C, L.dtype, L.N, frames[k].M);
+                by_class[{L.C, L.dtype, tc.G, tc.PPG}].push_back(k);
+            }
+        for (auto &kv : by_class) {
+            LaunchGroup g;
+            g.level = l;
+            g.C = kv.first[0];
+            g.dtype = kv.first[1];
+            const pilot_level &L0 = frames[kv.second[0]].level[l];
+            g.tc = choose_tile(ctx, g.C, g.dtype, L0.N, frames[kv.second[0]].M);
+            g.item_off = (int)plan.items.size();
+            g.tile_off = (int)plan.tiles.size();
+            for (int k : kv.second) {
+                const int slot = slot_of[k];
+                const int nht = (frames[k].M + g.tc.G - 1) / g.tc.G;
+                const int npt = n_ptiles_of(g.tc, frames[k].level[l].N);
+                for (int ht = 0; ht < nht; ++ht) {
+                    plan.tiles.push_back(TileItem{slot, ht, (int)plan.items.size() - g.item_off, npt});
+                    for (int pt = 0; pt < npt; ++pt) plan.items.push_back(WorkItem{slot, ht, pt, 0});
+                }
+            }
+            g.n_items = (int)plan.items.size() - g.item_off;
+            g.n_tiles = (int)plan.tiles.size() - g.tile_off;
+            g.passes = 1;
+            g.stat_class = class_index(l, g.C, g.dtype);
+            g.tc.grid = grid_of(ctx, g.tc, g.n_items);
+            plan.partial_floats = std::max(plan.partial_floats, (size_t)g.n_items * g.tc.G * kNV);
+            plan.groups.push_back(g);
+        }
+    }
+    int rc = ensure(ctx, ctx->partials, std::max<size_t>(1, plan.partial_floats) * sizeof(float), false, false);
+    if (rc) return rc;
+    const size_t ib = align256(std::max<size_t>(1, plan.items.size()) * sizeof(WorkItem));
+    const size_t tb = align256(std::max<size_t>(1, plan.tiles.size()) * sizeof(TileItem));
+    if ((rc = ensure(ctx, ctx->s_desc, ib + tb, false, false))) return rc;
+    int which;
+    char *h = (char *)stage_acquire(ctx, ib + tb, &which, &rc);
+    if (!h) return rc;
+    if (!plan.items.empty()) memcpy(h, plan.items.data(), plan.items.size() * sizeof(WorkItem));
+    if (!plan.tiles.empty()) memcpy(h + ib, plan.tiles.data(), plan.tiles.size() * sizeof(TileItem));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->s_desc.p, h, ib + tb, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipEventRecord(ctx->stage[which].ev, ctx->stream));
+    ctx->stage[which].pending = true;
+    ctx->serv_dirty = false;
+    return PILOT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pilot_admit_cost(pilot_ctx *ctx, const pilot_frame *frame, size_t *bytes)
+{
+    if (!ctx) return fail(nullptr, PILOT_EINVAL, "ctx: NULL");
+    if (!bytes) return fail(ctx, PILOT_EINVAL, "bytes: NULL");
+    int rc = validate_frame(ctx, frame, 0, false);
+    if (rc) return rc;
+    *bytes = frame_cost(ctx, *frame);
+    return PILOT_OK;
+}
+
+int pilot_admit(pilot_ctx *ctx, const pilot_frame *frame, const pilot_result *result, int *slot)
+{
+    if (!ctx) return fail(nullptr, PILOT_EINVAL, "ctx: NULL");
+    ctx->err.clear();
+    if (!slot) return fail(ctx, PILOT_EINVAL, "slot: NULL");
+    *slot = -1;
+    int rc = validate_frame(ctx, frame, 0, true);
+    if (rc) return rc;
+    if (!result || !result->poses_out || !result->cost || !result->iterations || !result->status || !result->best)
+        return fail(ctx, PILOT_EINVAL, "result: every output buffer must be non-NULL");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if ((rc = serving_init(ctx))) return rc;
+    const size_t cost = frame_cost(ctx, *frame);
+    if (ctx->budget && ctx->serv_bytes + cost > ctx->budget)
+        return fail(ctx, PILOT_EAGAIN, "HBM budget: %zu bytes in use + %zu needed > %zu", ctx->serv_bytes, cost, ctx->budget);
+    int s = -1;
+    for (int i = 0; i < (int)ctx->slots.size(); ++i)
+        if (!ctx->slots[i].active) {
+            s = i;
+            break;
+        }
+    if (s < 0) return fail(ctx, PILOT_EAGAIN, "all %d slots are busy", (int)ctx->slots.size());
+    const int base = arena_alloc(ctx, frame->M);
+    if (base < 0) return fail(ctx, PILOT_EAGAIN, "hypothesis arena full (%d hypotheses)", ctx->arena_cap);
+
+    FrameDev d;
+    fill_frame_dev(d, *frame, result, base);
+    d.slot = s;
+    d.done_flag = (int *)ctx->s_done.p + s;
+    int which;
+    char *h = (char *)stage_acquire(ctx, sizeof(FrameDev), &which, &rc);
+    if (!h) {
+        arena_release(ctx, base, frame->M);
+        return rc;
+    }
+    memcpy(h, &d, sizeof d);
+    FrameDev *dst = (FrameDev *)ctx->s_frames.p + s;
+    HIPCHK(ctx, hipMemcpyAsync(dst, h, sizeof d, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipEventRecord(ctx->stage[which].ev, ctx->stream));
+    ctx->stage[which].pending = true;
+    HIPCHK(ctx, launch_init(dst, 1, frame->M, (HypState *)ctx->hs.p, (PoseEval *)ctx->pose.p, (int *)ctx->hlev.p,
+                            MODE_LM, nullptr, 0, ctx->stream));
+    ServingSlot &sl = ctx->slots[s];
+    sl.active = true;
+    sl.M = frame->M;
+    sl.hyp_base = base;
+    sl.bytes = cost;
+    sl.admit_step = ctx->steps_enqueued;
+    sl.frame = *frame;
+    ctx->serv_bytes += cost;
+    ctx->serv_dirty = true;
+    *slot = s;
+    return PILOT_OK;
+}
+
+int pilot_step(pilot_ctx *ctx)
+{
+    if (!ctx) return fail(nullptr, PILOT_EINVAL, "ctx: NULL");
+    ctx->err.clear();
+    if (ctx->n_active() == 0) return PILOT_OK;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    int rc;
+    if (ctx->serv_dirty && (rc = serving_rebuild(ctx))) return rc;
+    // at most two steps in flight: step k+1 waits for step k-1
+    if (ctx->steps_enqueued >= 1) {
+        pilot_ctx::FlagBuf &old = ctx->flagbuf[(ctx->steps_enqueued - 1) % kFlagRing];
+        if (old.used && old.step == ctx->steps_enqueued - 1) HIPCHK(ctx, hipEventSynchronize(old.ev));
+    }
+    const Plan &plan = ctx->serv_plan;
+    const size_t ib = align256(std::max<size_t>(1, plan.items.size()) * sizeof(WorkItem));
+    DevPtrs dp;
+    dp.frames = (FrameDev *)ctx->s_frames.p;
+    dp.items = (WorkItem *)ctx->s_desc.p;
+    dp.tiles = (TileItem *)((char *)ctx->s_desc.p + ib);
+    for (int l = 0; l < PILOT_MAX_LEVELS; ++l)
+        for (const LaunchGroup &g : plan.groups)
+            if (g.level == l && (rc = enqueue_pass(ctx, plan, dp, g, MODE_LM, ctx->stream,
+                                                   (ctx->flags & PILOT_FLAG_PROFILE) != 0)))
+                return rc;
+    HIPCHK(ctx, launch_finalize(dp.frames, (int)ctx->slots.size(), (const HypState *)ctx->hs.p,
+                                (const int *)ctx->hlev.p, ctx->stream));
+    ctx->steps_enqueued++;
+    pilot_ctx::FlagBuf &fb = ctx->flagbuf[ctx->steps_enqueued % kFlagRing];
+    if (fb.used) HIPCHK(ctx, hipEventSynchronize(fb.ev));
+    HIPCHK(ctx, hipMemcpyAsync(fb.host, ctx->s_done.p, ctx->slots.size() * sizeof(int), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipEventRecord(fb.ev, ctx->stream));
+    fb.step = ctx->steps_enqueued;
+    fb.used = true;
+    return PILOT_OK;
+}
+
+int pilot_poll(pilot_ctx *ctx, int slot)
+{
+    if (!ctx) return fail(nullptr, PILOT_EINVAL, "ctx: NULL");
+    if (slot < 0 || slot >= (int)ctx->slots.size() || !ctx->slots[slot].active)
+        return fail(ctx, PILOT_EINVAL, "slot %d is not an active serving slot", slot);
+    ServingSlot &sl = ctx->slots[slot];
+    // newest completed flag copy taken after this slot's admission
+    const pilot_ctx::FlagBuf *best = nullptr;
+    for (const auto &fb : ctx->flagbuf) {
+        if (!fb.used || fb.step <= sl.admit_step) continue;
+        if (best && fb.step < best->step) continue;
+        const hipError_t q = hipEventQuery(fb.ev);
+        if (q == hipSuccess)
+            best = &fb;
+        else if (q != hipErrorNotReady)
+            return fail(ctx, PILOT_EDEVICE, "hipEventQuery: %s", hipGetErrorString(q));
+    }
+    if (!best || !best->host[slot]) return 0;
+    arena_release(ctx, sl.hyp_base, sl.M);
+    ctx->serv_bytes -= sl.bytes;
+    sl = ServingSlot();
+    ctx->serv_dirty = true;
+    return 1;
+}
+
+int pilot_sync(pilot_ctx *ctx)
+{
+    if (!ctx) return fail(nullptr, PILOT_EINVAL, "ctx: NULL");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return PILOT_OK;
+}
+
+int pilot_serving_state(pilot_ctx *ctx, int *active_slots, size_t *bytes_in_use)
+{
+    if (!ctx) return fail(nullptr, PILOT_EINVAL, "ctx: NULL");
+    if (active_slots) *active_slots = ctx->n_active();
+    if (bytes_in_use) *bytes_in_use = ctx->serv_bytes;
+    return PILOT_OK;
+}
 
 }  // extern "C"

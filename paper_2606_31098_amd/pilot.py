@@ -33,7 +33,8 @@ class DeviceFrame:
     """
 
     def __init__(self, frame, device: str = "cuda", dtype: str = "f32", share_points: bool = True,
-                 poses: Optional[np.ndarray] = None):
+                 poses: Optional[np.ndarray] = None, prior: Optional["torch.Tensor"] = None,
+                 prior_best: Optional["torch.Tensor"] = None, hyp_offsets: Optional[np.ndarray] = None):
         self.frame = frame
         self.keep: List[torch.Tensor] = []
         s = A.Frame()
@@ -63,10 +64,20 @@ class DeviceFrame:
                 if getattr(L, "ref_w", None) is not None else None
             lv.iters = int(L.iters)
             lv.loss_kind, lv.loss_scale = int(L.loss[0]), float(L.loss[1])
-        P = np.ascontiguousarray(frame.poses if poses is None else poses, dtype=np.float64)
-        self.poses = self._k(torch.as_tensor(P).to(device))
-        s.M = int(P.shape[0])
-        s.poses_in = self.poses.data_ptr()
+        if hyp_offsets is not None:
+            # hypotheses generated on the device around `prior` (row prior_best)
+            off = self._k(torch.as_tensor(np.ascontiguousarray(hyp_offsets, dtype=np.float64)).to(device))
+            s.M = int(off.shape[0])
+            s.hyp_offsets = off.data_ptr()
+            s.prior_poses = self._k(prior.to(device=device, dtype=torch.float64).contiguous()).data_ptr()
+            s.prior_best = _ptr(self._k(prior_best)) if prior_best is not None else None
+            s.poses_in = None
+            self.poses = None
+        else:
+            P = np.ascontiguousarray(frame.poses if poses is None else poses, dtype=np.float64)
+            self.poses = self._k(torch.as_tensor(P).to(device))
+            s.M = int(P.shape[0])
+            s.poses_in = self.poses.data_ptr()
         s.use_gravity = int(frame.use_gravity)
         s.gravity_loss_kind = int(frame.gravity_loss[0])
         s.gravity_loss_scale = float(frame.gravity_loss[1])
@@ -226,6 +237,9 @@ class Context:
 
     def poll(self, slot: int) -> bool:
         return self._check(self.lib.pilot_poll(self.h, slot)) == 1
+
+    def sync(self):
+        self._check(self.lib.pilot_sync(self.h))
 
     def serving_state(self):
         a, b = C.c_int(), C.c_size_t()

@@ -1,0 +1,113 @@
+"""Continuous-batching request loop over a libpilot context.
+
+Frames of several concurrent streams arrive over time.  A stream's frame is
+eligible once the stream's previous frame has finished (its result is the
+next frame's prior, kept on the device); eligible frames are admitted into
+solver slots while slots and the HBM budget allow (pilot_admit returns
+EAGAIN otherwise and the frame waits), and every loop turn advances all
+admitted frames by one LM pass (pilot_step) and collects finished ones
+(pilot_poll).  Frames admitted while others are running join the next pass,
+so their work overlaps on the device.
+
+The loop is generic: a request supplies its arrival time and a `prepare`
+callback that builds the frame's device inputs given the previous result of
+its stream.  It records arrival -> completion latency as observed on the
+host.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+from typing import Any, Callable, Dict, List, Optional
+
+
+@dataclass
+class Request:
+    stream: int
+    t_arrival: float                      # seconds from the start of the run
+    prepare: Callable[[Any], tuple]      # prev result (or None) -> (DeviceFrame, DeviceResult, keepalive)
+    tag: Any = None
+
+
+@dataclass
+class Completion:
+    request: Request
+    t_admit: float
+    t_done: float
+    result: Any
+    steps: int
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.request.t_arrival
+
+
+@dataclass
+class RunStats:
+    completions: List[Completion] = field(default_factory=list)
+    steps: int = 0
+    eagain: int = 0
+    max_active: int = 0
+    max_queue: int = 0
+    wall: float = 0.0
+    last_arrival: float = 0.0
+
+
+class ServingLoop:
+    def __init__(self, ctx, clock: Callable[[], float] = time.perf_counter):
+        self.ctx = ctx
+        self.clock = clock
+
+    def run(self, requests: List[Request], realtime: bool = True,
+            on_complete: Optional[Callable[[Completion], None]] = None) -> RunStats:
+        reqs = sorted(requests, key=lambda r: r.t_arrival)
+        st = RunStats(last_arrival=reqs[-1].t_arrival if reqs else 0.0)
+        queues: Dict[int, collections.deque] = collections.defaultdict(collections.deque)
+        busy: Dict[int, bool] = collections.defaultdict(bool)
+        prev: Dict[int, Any] = {}
+        active: Dict[int, tuple] = {}
+        t0 = self.clock()
+        nxt = 0
+        while nxt < len(reqs) or any(queues.values()) or active:
+            now = self.clock() - t0
+            if not realtime and not active and not any(queues.values()) and nxt < len(reqs):
+                now = max(now, reqs[nxt].t_arrival)      # skip idle time
+            while nxt < len(reqs) and reqs[nxt].t_arrival <= now:
+                queues[reqs[nxt].stream].append(reqs[nxt])
+                nxt += 1
+            st.max_queue = max(st.max_queue, sum(len(q) for q in queues.values()))
+            # admit the head of every idle stream, oldest arrival first
+            heads = sorted((q[0].t_arrival, s) for s, q in queues.items() if q and not busy[s])
+            for _, s in heads:
+                req = queues[s][0]
+                df, res, keep = req.prepare(prev.get(s))
+                slot = self.ctx.admit(df, res)
+                if slot is None:
+                    st.eagain += 1
+                    break                               # no slot or budget: retry after the next pass
+                queues[s].popleft()
+                busy[s] = True
+                active[slot] = (req, df, res, keep, self.clock() - t0, st.steps)
+            st.max_active = max(st.max_active, len(active))
+            if active:
+                self.ctx.step()
+                st.steps += 1
+            elif nxt < len(reqs) and realtime:
+                time.sleep(max(0.0, min(reqs[nxt].t_arrival - (self.clock() - t0), 0.002)))
+            for slot in list(active):
+                if self.ctx.poll(slot):
+                    req, df, res, keep, t_adm, s0 = active.pop(slot)
+                    c = Completion(req, t_adm, self.clock() - t0, res, st.steps - s0)
+                    st.completions.append(c)
+                    busy[req.stream] = False
+                    prev[req.stream] = res
+                    if on_complete:
+                        on_complete(c)
+            if not active and not any(queues.values()) and nxt >= len(reqs):
+                break
+            if active and not realtime:
+                pass
+        self.ctx.sync()
+        st.wall = self.clock() - t0
+        return st

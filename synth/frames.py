@@ -124,15 +124,17 @@ class Dsm:
         """Bilinear height with clamp-to-edge, float64 arithmetic on the
         float32 raster (the same surface a solver sees)."""
         Hd, Wd = self.heights.shape
-        D = self.heights.astype(np.float64)
+        D = self.heights
         fj = np.clip((np.asarray(x, np.float64) - self.x0) / self.gsd, 0.0, Wd - 1.0)
         fi = np.clip((np.asarray(y, np.float64) - self.y0) / self.gsd, 0.0, Hd - 1.0)
         j0 = np.minimum(np.floor(fj).astype(np.int64), Wd - 2)
         i0 = np.minimum(np.floor(fi).astype(np.int64), Hd - 2)
         a = fj - j0
         b = fi - i0
-        top = D[i0, j0] * (1.0 - a) + D[i0, j0 + 1] * a
-        bot = D[i0 + 1, j0] * (1.0 - a) + D[i0 + 1, j0 + 1] * a
+        d00, d01 = D[i0, j0].astype(np.float64), D[i0, j0 + 1].astype(np.float64)
+        d10, d11 = D[i0 + 1, j0].astype(np.float64), D[i0 + 1, j0 + 1].astype(np.float64)
+        top = d00 * (1.0 - a) + d01 * a
+        bot = d10 * (1.0 - a) + d11 * a
         return top * (1.0 - b) + bot * b
 
 
@@ -358,7 +360,8 @@ def make_frame(config: int = 2, frame: int = 0, *, noise: bool = True,
                N: Optional[int] = None, M: Optional[int] = None,
                level_shapes=None, iters=None, dsm_side: Optional[int] = None,
                seed: Optional[int] = None, feature_sigma: float = FEATURE_SIGMA_PX,
-               altitude: float = 150.0, pitch_deg: float = 45.0) -> Frame:
+               altitude: float = 150.0, pitch_deg: float = 45.0,
+               field_cache: Optional[dict] = None, field_key: int = 0) -> Frame:
     """One synthetic frame.
 
     config 1: 64x64 DSM, N=1024, M=1, one 120x160x32 level, 20 iterations.
@@ -367,6 +370,9 @@ def make_frame(config: int = 2, frame: int = 0, *, noise: bool = True,
     config 3: as config 2 with N=16384 and M=1024 (the caller rounds the maps
               and reference descriptors to bf16).
     Keyword arguments override the sizes (used for small test cases).
+    field_cache: optional dict shared across frames; the descriptor field of
+    an (H, W, C) level is then drawn once per (H, W, C, field_key) and reused
+    (each frame still gets its own anchors, poses and reference samples).
     """
     presets = {
         1: dict(dsm_side=64, N=1024, M=1, levels=[(120, 160, 32)], iters=[20]),
@@ -416,7 +422,14 @@ def make_frame(config: int = 2, frame: int = 0, *, noise: bool = True,
     levels = []
     for li, (H, W, C) in enumerate(p["levels"]):
         K = level_intrinsics(H, W)
-        F = make_field(r_fields[li], H, W, C, feature_sigma)
+        if field_cache is not None:
+            fk = (H, W, C, field_key)
+            if fk not in field_cache:
+                field_cache[fk] = make_field(np.random.default_rng(seed_for(9, H * 7 + W * 13 + C * 17 + 1009 * field_key)), H, W, C,
+                                             feature_sigma)
+            F = field_cache[fk]
+        else:
+            F = make_field(r_fields[li], H, W, C, feature_sigma)
         u, v, _ = _project(gt, K, P)
         ref = sample_field(F, u, v)
         if noise:
@@ -447,6 +460,35 @@ def make_frame(config: int = 2, frame: int = 0, *, noise: bool = True,
     return Frame(levels=levels, poses=poses, dsm=dsm, g_imu=g_imu, d_range=float(d), pc=pc,
                  gt_pose=gt, meta=dict(config=config, frame=frame, noise=noise,
                                        pitch=pitch, roll=roll, init_pose=init))
+
+
+def batch_config(n: int = 64, seed: int = seed_for(4, 0)):
+    """Shapes of the uneven batch: per frame N log-uniform in [2048, 32768],
+    M uniform in {32, 64, 128, 256, 512}, finest level one of 240x320,
+    360x480, 480x640 (levels at 1/4, 1/2, 1 of it with C = 32, 64, 128),
+    15 LM iterations per level."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        N = int(math.floor(math.exp(rng.uniform(math.log(2048), math.log(32768)))))
+        M = int(rng.choice([32, 64, 128, 256, 512]))
+        Hf, Wf = [(240, 320), (360, 480), (480, 640)][int(rng.integers(0, 3))]
+        levels = ((Hf // 4, Wf // 4, 32), (Hf // 2, Wf // 2, 64), (Hf, Wf, 128))
+        out.append(dict(N=N, M=M, level_shapes=levels, iters=(15, 15, 15)))
+    return out
+
+
+def make_batch(n: int = 64, field_pool: int = 8, progress=None) -> List[Frame]:
+    """The uneven batch (see batch_config); descriptor fields come from a pool
+    of `field_pool` fields per level shape (frames keep their own anchors,
+    poses, DSM and reference samples)."""
+    cache: dict = {}
+    frames = []
+    for i, kw in enumerate(batch_config(n)):
+        frames.append(make_frame(4, i, dsm_side=256, field_cache=cache, field_key=i % field_pool, **kw))
+        if progress:
+            progress(i)
+    return frames
 
 
 # --------------------------------------------------------------------------

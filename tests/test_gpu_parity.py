@@ -57,7 +57,7 @@ def test_normal_equations_match_oracle(ctx, dtype):
             Ho, go, co, no = oracle.linearize(of, lvl, poses[m])
             err = rel_frobenius(np.concatenate([H[m], g[m][:, None]], 1), np.concatenate([Ho, go[:, None]], 1))
             assert err <= NEQ_TOL, (lvl, m, err)
-            assert abs(cost[m] - co) <= 1e-5 * abs(co), (lvl, m, cost[m], co)
+            assert abs(cost[m] - co) <= 1e-9 * abs(co), (lvl, m, cost[m], co)   # FP64 cost path
             assert abs(int(n[m]) - no) <= border_count(f.levels[lvl], poses[m]), (lvl, m, n[m], no)
 
 
