@@ -38,8 +38,8 @@
  *              stops the level, STALLED); an accepted step with
  *              |d rho| < step_tol_t and |d omega| < step_tol_r ends the level
  *              (CONVERGED); every iteration, accepted or not, counts.
- *   selection  best = lowest final cost among non-degenerate hypotheses,
- *              ties to the lowest index, -1 if none.
+ *   selection  best = lowest final cost among hypotheses that are neither
+ *              degenerate nor pruned, ties to the lowest index, -1 if none.
  *
  * Threading: a pilot_ctx is used by one host thread at a time; several
  * contexts may share a device.  All work is enqueued on the context's stream
@@ -70,7 +70,7 @@ enum {
 
 enum { PILOT_F32 = 0, PILOT_BF16 = 1 };
 enum { PILOT_LOSS_CAUCHY = 0, PILOT_LOSS_HUBER = 1, PILOT_LOSS_L2 = 2 };
-enum { PILOT_CONVERGED = 0, PILOT_MAX_ITERS = 1, PILOT_STALLED = 2, PILOT_DEGENERATE = 3 };
+enum { PILOT_CONVERGED = 0, PILOT_MAX_ITERS = 1, PILOT_STALLED = 2, PILOT_DEGENERATE = 3, PILOT_PRUNED = 4 };
 
 /* pilot_config.flags */
 enum {
@@ -146,6 +146,14 @@ typedef struct {
     const double *prior_poses;  /* device, rows of 12                              */
     const int32_t *prior_best;  /* device, 1 index, or NULL                         */
     const double *hyp_offsets;  /* device, M*3: dx, dy, dyaw                        */
+    /* Top-K pruning (supplement, Multi-Hypothesis Refinement): once every
+     * hypothesis has finished level prune_level, only the keep_top lowest
+     * costs (ties to the lower index; degenerate ones excluded) continue to
+     * the finer levels; the others end with status PILOT_PRUNED and keep
+     * their pose and cost of that level.  keep_top = 0: no pruning.
+     * Requires 0 <= prune_level < n_levels - 1 and M <= 8192. */
+    int32_t keep_top;
+    int32_t prune_level;
 } pilot_frame;
 
 /* Caller-owned device buffers. */
@@ -153,7 +161,7 @@ typedef struct {
     double *poses_out;          /* M*12 final poses                                   */
     double *cost;               /* M final total cost (finest level)                  */
     int32_t *iterations;        /* M iterations executed, all levels                  */
-    int32_t *status;            /* M PILOT_CONVERGED .. PILOT_DEGENERATE              */
+    int32_t *status;            /* M PILOT_CONVERGED .. PILOT_PRUNED                  */
     int32_t *best;              /* 1 index (or -1)                                    */
 } pilot_result;
 

@@ -22,7 +22,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 # a test may point the wrapper at a deliberately broken build of oracle.c
 _LIB_OVERRIDE = os.environ.get("PILOT_ORACLE_LIB_OVERRIDE")
 
-CONVERGED, MAX_ITERS, STALLED, DEGENERATE = 0, 1, 2, 3
+CONVERGED, MAX_ITERS, STALLED, DEGENERATE, PRUNED = 0, 1, 2, 3, 4
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
@@ -47,7 +47,7 @@ class _Frame(C.Structure):
                 ("tau", C.c_double), ("up", C.c_double), ("down", C.c_double),
                 ("lam_min_rel", C.c_double), ("lam_max_rel", C.c_double),
                 ("tol_t", C.c_double), ("tol_r", C.c_double), ("z_min", C.c_double),
-                ("min_valid", C.c_int)]
+                ("min_valid", C.c_int), ("keep_top", C.c_int), ("prune_level", C.c_int)]
 
 
 def build(force: bool = True) -> str:
@@ -151,6 +151,8 @@ class OracleFrame:
         s.lam_min_rel, s.lam_max_rel = lm["lambda_min_rel"], lm["lambda_max_rel"]
         s.tol_t, s.tol_r, s.z_min = lm["step_tol_t"], lm["step_tol_r"], lm["z_min"]
         s.min_valid = int(lm["min_valid"])
+        s.keep_top = int(getattr(frame, "keep_top", 0))
+        s.prune_level = int(getattr(frame, "prune_level", 0))
         self.s = s
         self.ptr = C.pointer(s)
 
@@ -233,7 +235,8 @@ def cholesky_solve6(A, b):
 
 
 def solve(frame, hyps=None, threads=None, trace=False, of: OracleFrame = None):
-    """Run the oracle LM on hypotheses `hyps` (indices, default all).
+    """Run the oracle LM on hypotheses `hyps` (indices, default all; with
+    top-K pruning the ranking is among the solved hypotheses).
 
     Returns dict with poses (k,12), cost (k), iterations (k), status (k),
     best (index into the full hypothesis set among the solved ones, or -1)

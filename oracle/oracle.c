@@ -22,6 +22,7 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
 #include <omp.h>
@@ -471,87 +472,120 @@ static int all_finite(const double *a, int n)
 /* the candidate Exp(dxi) T of Eq. (9) is re-evaluated on the total        */
 /* objective and accepted iff its cost is lower.                           */
 /* ------------------------------------------------------------------ */
-static void solve_one(const orc_frame *f, const double *pose_in, double *pose_out,
-                      double *cost_out, int *it_out, int *status_out,
-                      double *trace, int trace_stride)
+typedef struct {
+    double T[12];
+    double c;
+    int status, total_it, row, finished;
+} hyp_state;
+
+/* One level of LM for one hypothesis. */
+static void run_level(const orc_frame *f, int l, hyp_state *st, double *trace, int trace_stride)
 {
-    double T[12], H[36], g[6], c;
+    double H[36], g[6], c;
     int n;
-    memcpy(T, pose_in, sizeof(T));
-    int status = ORC_MAX_ITERS, total_it = 0, row = 0;
-    c = NAN;
-    for (int l = 0; l < f->n_levels; ++l) {
-        orc_linearize(f, l, T, H, g, &c, &n);
-        double D = 0.0;
-        for (int i = 0; i < 6; ++i)
-            if (H[7 * i] > D) D = H[7 * i];
-        if (n < f->min_valid || !isfinite(c) || !all_finite(H, 36) || !all_finite(g, 6) || !(D > 0.0)) {
-            status = ORC_DEGENERATE;
-            break;
-        }
-        double lam = f->tau * D, lam_min = f->lam_min_rel * D, lam_max = f->lam_max_rel * D;
-        int lvl_status = ORC_MAX_ITERS;
-        for (int it = 0; it < f->lv[l].iters; ++it) {
-            total_it++;
-            double A[36], mg[6], dx[6];
-            memcpy(A, H, sizeof(A));
-            for (int i = 0; i < 6; ++i) {
-                A[7 * i] += lam;
-                mg[i] = -g[i];
-            }
-            double *tr = (trace && row < trace_stride) ? trace + 4 * row : NULL;
-            row++;
-            if (orc_cholesky_solve6(A, mg, dx) != 0) {
-                if (tr) { tr[0] = l; tr[1] = c; tr[2] = NAN; tr[3] = 0; }
-                lam *= f->up;
-                if (lam >= lam_max) { lvl_status = ORC_STALLED; break; }
-                continue;
-            }
-            double E[12], Tc[12], Hc[36], gc[6], cc;
-            int nc;
-            orc_exp(dx, E);
-            orc_compose(E, T, Tc);
-            orc_linearize(f, l, Tc, Hc, gc, &cc, &nc);
-            if (tr) { tr[0] = l; tr[1] = c; tr[2] = cc; tr[3] = 0; }
-            if (cc < c) {
-                if (tr) tr[3] = 1;
-                memcpy(T, Tc, sizeof(T));
-                memcpy(H, Hc, sizeof(H));
-                memcpy(g, gc, sizeof(g));
-                c = cc;
-                n = nc;
-                lam = lam / f->down;
-                if (lam < lam_min) lam = lam_min;
-                double nt = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
-                double nr = sqrt(dx[3] * dx[3] + dx[4] * dx[4] + dx[5] * dx[5]);
-                if (nt < f->tol_t && nr < f->tol_r) { lvl_status = ORC_CONVERGED; break; }
-            } else {
-                lam *= f->up;
-                if (lam >= lam_max) { lvl_status = ORC_STALLED; break; }
-            }
-        }
-        status = lvl_status;
+    orc_linearize(f, l, st->T, H, g, &c, &n);
+    st->c = c;
+    double D = 0.0;
+    for (int i = 0; i < 6; ++i)
+        if (H[7 * i] > D) D = H[7 * i];
+    if (n < f->min_valid || !isfinite(c) || !all_finite(H, 36) || !all_finite(g, 6) || !(D > 0.0)) {
+        st->status = ORC_DEGENERATE;
+        st->finished = 1;
+        return;
     }
-    memcpy(pose_out, T, sizeof(T));
-    *cost_out = c;
-    *it_out = total_it;
-    *status_out = status;
+    double lam = f->tau * D, lam_min = f->lam_min_rel * D, lam_max = f->lam_max_rel * D;
+    int lvl_status = ORC_MAX_ITERS;
+    for (int it = 0; it < f->lv[l].iters; ++it) {
+        st->total_it++;
+        double A[36], mg[6], dx[6];
+        memcpy(A, H, sizeof(A));
+        for (int i = 0; i < 6; ++i) {
+            A[7 * i] += lam;
+            mg[i] = -g[i];
+        }
+        double *tr = (trace && st->row < trace_stride) ? trace + 4 * st->row : NULL;
+        st->row++;
+        if (orc_cholesky_solve6(A, mg, dx) != 0) {
+            if (tr) { tr[0] = l; tr[1] = c; tr[2] = NAN; tr[3] = 0; }
+            lam *= f->up;
+            if (lam >= lam_max) { lvl_status = ORC_STALLED; break; }
+            continue;
+        }
+        double E[12], Tc[12], Hc[36], gc[6], cc;
+        int nc;
+        orc_exp(dx, E);
+        orc_compose(E, st->T, Tc);
+        orc_linearize(f, l, Tc, Hc, gc, &cc, &nc);
+        if (tr) { tr[0] = l; tr[1] = c; tr[2] = cc; tr[3] = 0; }
+        if (cc < c) {
+            if (tr) tr[3] = 1;
+            memcpy(st->T, Tc, sizeof(Tc));
+            memcpy(H, Hc, sizeof(H));
+            memcpy(g, gc, sizeof(g));
+            c = cc;
+            st->c = c;
+            lam = lam / f->down;
+            if (lam < lam_min) lam = lam_min;
+            double nt = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
+            double nr = sqrt(dx[3] * dx[3] + dx[4] * dx[4] + dx[5] * dx[5]);
+            if (nt < f->tol_t && nr < f->tol_r) { lvl_status = ORC_CONVERGED; break; }
+        } else {
+            lam *= f->up;
+            if (lam >= lam_max) { lvl_status = ORC_STALLED; break; }
+        }
+    }
+    st->status = lvl_status;
 }
 
 void orc_solve(const orc_frame *f, const double *poses_in, int m0, int m1,
                double *poses_out, double *cost, int *iterations, int *status,
                double *trace, int trace_stride)
 {
+    const int k = m1 - m0;
     if (trace)
-        for (long i = 0; i < (long)(m1 - m0) * trace_stride * 4; ++i) trace[i] = NAN;
+        for (long i = 0; i < (long)k * trace_stride * 4; ++i) trace[i] = NAN;
+    hyp_state *st = (hyp_state *)calloc((size_t)(k > 0 ? k : 1), sizeof(hyp_state));
+    for (int i = 0; i < k; ++i) {
+        memcpy(st[i].T, poses_in + 12 * (size_t)(m0 + i), sizeof(st[i].T));
+        st[i].c = NAN;
+        st[i].status = ORC_MAX_ITERS;
+    }
+    const int prune = f->keep_top > 0 && f->prune_level >= 0 && f->prune_level < f->n_levels - 1;
+    const int split = prune ? f->prune_level + 1 : f->n_levels;
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 1) num_threads(orc_get_threads())
 #endif
-    for (int m = m0; m < m1; ++m) {
-        solve_one(f, poses_in + 12 * (size_t)m, poses_out + 12 * (size_t)m, cost + m,
-                  iterations + m, status + m,
-                  trace ? trace + (size_t)(m - m0) * trace_stride * 4 : NULL, trace_stride);
+    for (int i = 0; i < k; ++i)
+        for (int l = 0; l < split && !st[i].finished; ++l)
+            run_level(f, l, &st[i], trace ? trace + (size_t)i * trace_stride * 4 : NULL, trace_stride);
+    if (prune) {
+        /* rank by the cost after the pruning level: lower cost first, ties
+         * to the lower index; degenerate hypotheses are not ranked */
+        for (int i = 0; i < k; ++i) {
+            if (st[i].finished) continue;
+            int better = 0;
+            for (int j = 0; j < k; ++j) {
+                if (j == i || st[j].finished) continue;
+                if (st[j].c < st[i].c || (st[j].c == st[i].c && j < i)) better++;
+            }
+            if (better >= f->keep_top) st[i].status = ORC_PRUNED;
+        }
+        for (int i = 0; i < k; ++i)
+            if (st[i].status == ORC_PRUNED) st[i].finished = 1;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(orc_get_threads())
+#endif
+        for (int i = 0; i < k; ++i)
+            for (int l = split; l < f->n_levels && !st[i].finished; ++l)
+                run_level(f, l, &st[i], trace ? trace + (size_t)i * trace_stride * 4 : NULL, trace_stride);
     }
+    for (int i = 0; i < k; ++i) {
+        memcpy(poses_out + 12 * (size_t)(m0 + i), st[i].T, sizeof(st[i].T));
+        cost[m0 + i] = st[i].c;
+        iterations[m0 + i] = st[i].total_it;
+        status[m0 + i] = st[i].status;
+    }
+    free(st);
 }
 
 /* Selection of the output pose: the hypothesis with the lowest final
@@ -561,7 +595,7 @@ int orc_best(const double *cost, const int *status, int M)
 {
     int best = -1;
     for (int m = 0; m < M; ++m) {
-        if (status[m] == ORC_DEGENERATE || !isfinite(cost[m])) continue;
+        if (status[m] == ORC_DEGENERATE || status[m] == ORC_PRUNED || !isfinite(cost[m])) continue;
         if (best < 0 || cost[m] < cost[best]) best = m;
     }
     return best;

@@ -24,7 +24,7 @@ extern "C" {
 #endif
 
 enum { ORC_CAUCHY = 0, ORC_HUBER = 1, ORC_L2 = 2 };
-enum { ORC_CONVERGED = 0, ORC_MAX_ITERS = 1, ORC_STALLED = 2, ORC_DEGENERATE = 3 };
+enum { ORC_CONVERGED = 0, ORC_MAX_ITERS = 1, ORC_STALLED = 2, ORC_DEGENERATE = 3, ORC_PRUNED = 4 };
 
 typedef struct {
     int H, W, C;
@@ -56,6 +56,10 @@ typedef struct {
     double dsm_x0, dsm_y0, dsm_gsd;
     double tau, up, down, lam_min_rel, lam_max_rel, tol_t, tol_r, z_min;
     int min_valid;
+    /* top-K pruning (supplement, Multi-Hypothesis Refinement): after level
+     * prune_level every hypothesis has finished that level; only the keep_top
+     * lowest costs continue (0 = no pruning) */
+    int keep_top, prune_level;
 } orc_frame;
 
 /* SE(3) */
@@ -94,6 +98,7 @@ void orc_linearize(const orc_frame *f, int l, const double T[12],
 int orc_cholesky_solve6(const double A[36], const double b[6], double x[6]);
 
 /* LM over hypotheses [m0, m1) of poses_in (M*12).  Outputs are indexed by m.
+ * With pruning, the ranking is over the hypotheses in [m0, m1).
  * trace (optional): per hypothesis `trace_stride` rows of 4 doubles
  * (level, cost before, candidate cost or NaN, accepted 0/1), one row per
  * iteration; unused rows are NaN. */

@@ -11,7 +11,7 @@ MAX_LEVELS = 4
 OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 F32, BF16 = 0, 1
 LOSS_CAUCHY, LOSS_HUBER, LOSS_L2 = 0, 1, 2
-CONVERGED, MAX_ITERS, STALLED, DEGENERATE = 0, 1, 2, 3
+CONVERGED, MAX_ITERS, STALLED, DEGENERATE, PRUNED = 0, 1, 2, 3, 4
 FLAG_NO_GRAPH, FLAG_AUTOTUNE, FLAG_PROFILE = 1, 2, 4
 
 ERROR_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE",
@@ -50,7 +50,8 @@ class Frame(C.Structure):
                 ("lambda_min_rel", C.c_double), ("lambda_max_rel", C.c_double),
                 ("step_tol_t", C.c_double), ("step_tol_r", C.c_double), ("z_min", C.c_double),
                 ("min_valid", C.c_int32), ("reserved", C.c_int32),
-                ("prior_poses", _dp), ("prior_best", _vp), ("hyp_offsets", _dp)]
+                ("prior_poses", _dp), ("prior_best", _vp), ("hyp_offsets", _dp),
+                ("keep_top", C.c_int32), ("prune_level", C.c_int32)]
 
 
 class Result(C.Structure):

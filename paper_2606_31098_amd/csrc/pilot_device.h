@@ -59,7 +59,7 @@ struct FrameDev {
     double *diag_H, *diag_g, *diag_cost;
     int *diag_n;
     int *done_flag;   // serving: set to 1 by the finalize step
-    int pad0, pad1;
+    int keep_top, prune_level;
 };
 
 // A tile of G hypotheses x P anchors of one frame at one level.
@@ -90,7 +90,9 @@ struct HypState {
 };
 
 enum { PHASE_START = 0, PHASE_CAND = 1 };
-enum { ST_CONVERGED = 0, ST_MAX_ITERS = 1, ST_STALLED = 2, ST_DEGENERATE = 3 };
+enum { ST_CONVERGED = 0, ST_MAX_ITERS = 1, ST_STALLED = 2, ST_DEGENERATE = 3, ST_PRUNED = 4 };
+constexpr int HLEV_DONE = -1;       // finished
+constexpr int HLEV_WAIT = -2;       // finished the pruning level, waiting for the ranking
 enum { MODE_LM = 0, MODE_DIAG = 1 };
 
 // Pose a hypothesis is evaluated at in the next pass: R row-major (9), t (3),

@@ -29,6 +29,10 @@ hipError_t launch_init(const FrameDev *frames, int n_frames, int max_M, HypState
                        PoseEval *pose, int *hlev, int mode, const double *diag_poses,
                        int diag_level, hipStream_t s);
 
+// Top-K pruning of frames whose hypotheses all finished their pruning level.
+hipError_t launch_prune(const FrameDev *frames, int n_frames, HypState *hs, PoseEval *pose, int *hlev,
+                        hipStream_t s);
+
 // Write results of every frame whose hypotheses have all finished and that
 // has not been finalised yet (done_flag == 0), including the argmin.
 hipError_t launch_finalize(const FrameDev *frames, int n_frames, const HypState *hs,

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const FrameDev *frames, c
         f.cost_out[m] = s.cost;
         f.iters_out[m] = s.it_total;
         f.status_out[m] = s.status;
-        if (s.status != ST_DEGENERATE && isfinite(s.cost) && (bi < 0 || s.cost < bc)) {
+        if (s.status != ST_DEGENERATE && s.status != ST_PRUNED && isfinite(s.cost) && (bi < 0 || s.cost < bc)) {
             bc = s.cost;
             bi = m;
         }
@@ -251,6 +251,55 @@ __global__ __launch_bounds__(256) void finalize_kernel(const FrameDev *frames, c
             *f.done_flag = 1;
         }
     }
+}
+
+// Top-K pruning, one block per frame: once no hypothesis of the frame is
+// still at or before its pruning level (all are waiting or finished), rank
+// the waiting ones by cost (ties to the lower index) and let the keep_top
+// best continue at the next level; the others end as PRUNED.
+constexpr int kPruneMaxM = 8192;
+
+__global__ __launch_bounds__(256) void prune_kernel(const FrameDev *frames, HypState *hs, PoseEval *pose,
+                                                     int *hlev)
+{
+    const FrameDev &f = frames[blockIdx.x];
+    if (f.M <= 0 || f.keep_top <= 0) return;
+    __shared__ double s_cost[kPruneMaxM];
+    int waiting = 0, busy = 0;
+    for (int m = threadIdx.x; m < f.M; m += blockDim.x) {
+        const int h = hlev[f.hyp_base + m];
+        waiting |= (h == HLEV_WAIT);
+        busy |= (h >= 0 && h <= f.prune_level);
+        const double c = hs[f.hyp_base + m].cost;
+        s_cost[m] = (h == HLEV_WAIT) ? (isnan(c) ? __longlong_as_double(0x7ff0000000000000LL) : c)
+                                     : __longlong_as_double(0x7ff8000000000000LL);   // NaN: not ranked
+    }
+    if (!__syncthreads_or(waiting) || __syncthreads_or(busy)) return;
+    for (int m = threadIdx.x; m < f.M; m += blockDim.x) {
+        const double cm = s_cost[m];
+        if (isnan(cm)) continue;
+        int better = 0;
+        for (int j = 0; j < f.M; ++j) {
+            const double cj = s_cost[j];
+            better += (!isnan(cj) && (cj < cm || (cj == cm && j < m))) ? 1 : 0;
+        }
+        HypState &s = hs[f.hyp_base + m];
+        if (better < f.keep_top) {
+            s.level = f.prune_level + 1;
+            s.phase = PHASE_START;
+            for (int i = 0; i < 12; ++i) pose[f.hyp_base + m].v[i] = s.T[i];
+            hlev[f.hyp_base + m] = s.level;
+        } else {
+            s.status = ST_PRUNED;
+            hlev[f.hyp_base + m] = HLEV_DONE;
+        }
+    }
+}
+
+hipError_t launch_prune(const FrameDev *frames, int n_frames, HypState *hs, PoseEval *pose, int *hlev, hipStream_t s)
+{
+    hipLaunchKernelGGL(prune_kernel, dim3(n_frames), dim3(256), 0, s, frames, hs, pose, hlev);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const FrameDev *frames, int n_frames, const HypState *hs, const int *hlev,

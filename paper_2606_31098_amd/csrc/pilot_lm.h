@@ -200,7 +200,9 @@ __device__ inline void store_pose(PoseEval &p, const double T[12])
 __device__ inline void level_done(const FrameDev &f, HypState &s, int st, PoseEval &p32, int &hlev)
 {
     s.status = st;
-    if (s.level + 1 < f.n_levels) {
+    if (f.keep_top > 0 && s.level == f.prune_level && s.level + 1 < f.n_levels) {
+        hlev = HLEV_WAIT;                          // the pruning kernel decides who continues
+    } else if (s.level + 1 < f.n_levels) {
         s.level += 1;
         s.phase = PHASE_START;
         store_pose(p32, s.T);

@@ -245,6 +245,12 @@ int validate_frame(pilot_ctx *ctx, const pilot_frame *f, int fi, bool need_poses
         return fail(ctx, PILOT_EINVAL, "frames[%d].step_tol_t/r: must be finite and >= 0", fi);
     if (!(f->z_min >= 0) || !std::isfinite(f->z_min)) return fail(ctx, PILOT_EINVAL, "frames[%d].z_min: must be finite and >= 0", fi);
     if (f->min_valid < 0) return fail(ctx, PILOT_EINVAL, "frames[%d].min_valid: must be >= 0", fi);
+    if (f->keep_top < 0) return fail(ctx, PILOT_EINVAL, "frames[%d].keep_top: must be >= 0", fi);
+    if (f->keep_top > 0) {
+        if (f->prune_level < 0 || f->prune_level >= f->n_levels - 1)
+            return fail(ctx, PILOT_EINVAL, "frames[%d].prune_level: must be 0..n_levels-2 with keep_top > 0", fi);
+        if (f->M > 8192) return fail(ctx, PILOT_EUNSUPPORTED, "frames[%d].keep_top: pruning supports M <= 8192", fi);
+    }
     return PILOT_OK;
 }
 
@@ -417,6 +423,8 @@ void fill_frame_dev(FrameDev &d, const pilot_frame &f, const pilot_result *r, in
     d.lmax_rel = f.lambda_max_rel;
     d.tol_t = f.step_tol_t;
     d.tol_r = f.step_tol_r;
+    d.keep_top = f.keep_top;
+    d.prune_level = f.prune_level;
     d.z_min = f.z_min;
     d.min_valid = f.min_valid;
     d.poses_in = f.poses_in;
@@ -607,6 +615,11 @@ int enqueue_schedule(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, hipStr
                     int rc = enqueue_pass(ctx, plan, dp, g, MODE_LM, s, timed);
                     if (rc) return rc;
                 }
+        bool prunes = false;
+        for (const FrameDev &f : plan.frames) prunes = prunes || (f.keep_top > 0 && f.prune_level == l);
+        if (prunes)
+            HIPCHK(ctx, launch_prune(dp.frames, (int)plan.frames.size(), (HypState *)ctx->hs.p, (PoseEval *)ctx->pose.p,
+                                     (int *)ctx->hlev.p, s));
     }
     HIPCHK(ctx, launch_finalize(dp.frames, (int)plan.frames.size(), (const HypState *)ctx->hs.p,
                                 (const int *)ctx->hlev.p, s));
@@ -1171,6 +1184,11 @@ int pilot_step(pilot_ctx *ctx)
             if (g.level == l && (rc = enqueue_pass(ctx, plan, dp, g, MODE_LM, ctx->stream,
                                                    (ctx->flags & PILOT_FLAG_PROFILE) != 0)))
                 return rc;
+    bool prunes = false;
+    for (const ServingSlot &sl : ctx->slots) prunes = prunes || (sl.active && sl.frame.keep_top > 0);
+    if (prunes)
+        HIPCHK(ctx, launch_prune(dp.frames, (int)ctx->slots.size(), (HypState *)ctx->hs.p, (PoseEval *)ctx->pose.p,
+                                 (int *)ctx->hlev.p, ctx->stream));
     HIPCHK(ctx, launch_finalize(dp.frames, (int)ctx->slots.size(), (const HypState *)ctx->hs.p,
                                 (const int *)ctx->hlev.p, ctx->stream));
     ctx->steps_enqueued++;

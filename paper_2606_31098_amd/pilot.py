@@ -99,6 +99,8 @@ class DeviceFrame:
         s.lambda_min_rel, s.lambda_max_rel = lm["lambda_min_rel"], lm["lambda_max_rel"]
         s.step_tol_t, s.step_tol_r, s.z_min = lm["step_tol_t"], lm["step_tol_r"], lm["z_min"]
         s.min_valid = int(lm["min_valid"])
+        s.keep_top = int(getattr(frame, "keep_top", 0))
+        s.prune_level = int(getattr(frame, "prune_level", 0))
         self.s = s
 
     def _k(self, t: torch.Tensor) -> torch.Tensor:

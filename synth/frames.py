@@ -262,6 +262,8 @@ class Frame:
     lm: dict = field(default_factory=lambda: dict(LM_DEFAULTS))
     gt_pose: Optional[np.ndarray] = None
     meta: dict = field(default_factory=dict)
+    keep_top: int = 0                   # top-K pruning after prune_level (0 = none)
+    prune_level: int = 0
 
     @property
     def M(self) -> int:
@@ -460,6 +462,19 @@ def make_frame(config: int = 2, frame: int = 0, *, noise: bool = True,
     return Frame(levels=levels, poses=poses, dsm=dsm, g_imu=g_imu, d_range=float(d), pc=pc,
                  gt_pose=gt, meta=dict(config=config, frame=frame, noise=noise,
                                        pitch=pitch, roll=roll, init_pose=init))
+
+
+def paper_shaped_frame(frame: int = 0) -> Frame:
+    """The paper's own online workload shape (Experiments, Implementation
+    Details; supplement, Multi-Hypothesis Refinement): 500 anchors, the
+    1210-hypothesis (x, y, yaw) grid around the prior, top 128 kept after the
+    coarse level, 2/3/4 iterations coarse to fine, 32-channel descriptors at
+    every level (sizes as the default pyramid)."""
+    f = make_frame(0, frame, N=500, M=1, level_shapes=((120, 160, 32), (240, 320, 32), (480, 640, 32)),
+                   iters=(2, 3, 4), dsm_side=256)
+    f.poses = grid_hypotheses(f.meta["init_pose"])
+    f.keep_top, f.prune_level = 128, 0
+    return f
 
 
 def batch_config(n: int = 64, seed: int = seed_for(4, 0)):

@@ -142,3 +142,20 @@ def test_empty_anchor_level_and_zero_iterations(ctx):
     rows, fails = compare_solutions(f, gpu, orc, POSE_TOL_M, POSE_TOL_DEG, "empty")
     assert not fails, fails
     assert np.all(gpu["status"] == orc["status"])
+
+
+def test_paper_grid_with_top_k_pruning_matches_oracle(ctx):
+    """1210 hypotheses on the paper's (x, y, yaw) grid, top 128 kept after the
+    coarse level: same survivors and same final poses as the oracle."""
+    f = S.make_frame(2, 7, N=500, M=1, level_shapes=((60, 80, 32), (120, 160, 32), (240, 320, 32)),
+                     iters=(2, 3, 4), dsm_side=128, seed=99)
+    f.poses = S.grid_hypotheses(f.meta["init_pose"])
+    f.keep_top, f.prune_level = 128, 0
+    say("solve 1210-hypothesis grid with top-128 pruning")
+    gpu = solve_gpu(ctx, f)
+    orc = oracle.solve(f, threads=8)
+    assert np.array_equal(gpu["status"] == 4, orc["status"] == 4)
+    assert int(np.sum(orc["status"] != 4)) <= 128
+    rows, fails = compare_solutions(f, gpu, orc, POSE_TOL_M, POSE_TOL_DEG, "grid")
+    assert not fails, fails[:10]
+    assert check_best(f, gpu, orc, POSE_TOL_M, POSE_TOL_DEG)

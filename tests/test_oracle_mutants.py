@@ -29,7 +29,9 @@ MUTANTS = {
     "cholesky_backsub_index": ("s -= L[6 * k + i] * x[k];", "s -= L[6 * i + k] * x[k];"),
     "out_of_view_penalty": ("2.0 * wr, &rho, &drho", "wr, &rho, &drho"),
     "lm_damping_direction": ("lam = lam / f->down;", "lam = lam * f->down;"),
-    "acceptance_rule": ("if (cc < c) {\n                if (tr) tr[3] = 1;", "if (cc < c + 1e-3 * fabs(c)) {\n                if (tr) tr[3] = 1;"),
+    "acceptance_rule": ("if (cc < c) {\n            if (tr) tr[3] = 1;", "if (cc < c + 1e-3 * fabs(c)) {\n            if (tr) tr[3] = 1;"),
+    "pruning_rank_direction": ("if (st[j].c < st[i].c || (st[j].c == st[i].c && j < i)) better++;",
+                               "if (st[j].c > st[i].c || (st[j].c == st[i].c && j < i)) better++;"),
     "selection_tie": ("if (best < 0 || cost[m] < cost[best]) best = m;",
                       "if (best < 0 || cost[m] <= cost[best]) best = m;"),
     "gravity_prior_weight": ("c += f->lambda_imu * rho;", "c += rho;"),

@@ -361,6 +361,29 @@ def test_accepted_costs_never_increase():
             assert np.all(R[~acc & ~np.isnan(R[:, 2]), 2] >= R[~acc & ~np.isnan(R[:, 2]), 1])
 
 
+def test_top_k_pruning_keeps_the_lowest_post_coarse_costs():
+    """Supplement, Multi-Hypothesis Refinement: after the coarse level only the
+    best-ranked hypotheses continue.  The survivors must be exactly the K
+    lowest costs of a run that stops after the coarse level."""
+    f = S.make_frame(2, 4, N=300, M=12, level_shapes=((30, 40, 16), (60, 80, 32)), iters=(4, 3),
+                     dsm_side=128, seed=77)
+    coarse_only = S.make_frame(2, 4, N=300, M=12, level_shapes=((30, 40, 16),), iters=(4,),
+                               dsm_side=128, seed=77)
+    r0 = oracle.solve(coarse_only, threads=4)
+    f.keep_top, f.prune_level = 5, 0
+    r = oracle.solve(f, threads=4)
+    alive = r0["status"] != oracle.DEGENERATE
+    order = sorted(np.flatnonzero(alive), key=lambda m: (r0["cost"][m], m))
+    expect = set(order[:5])
+    kept = set(np.flatnonzero(r["status"] != oracle.PRUNED)) - set(np.flatnonzero(~alive))
+    assert kept == expect
+    for m in range(f.M):
+        if r["status"][m] == oracle.PRUNED:       # pruned: pose and cost stay at the coarse result
+            assert np.array_equal(r["poses"][m], r0["poses"][m]) and r["cost"][m] == r0["cost"][m]
+            assert r["iterations"][m] == r0["iterations"][m]
+    assert r["best"] in expect
+
+
 def test_selection_rule():
     cost = np.array([3.0, np.nan, 1.0, 1.0, 0.5])
     st = np.array([1, 1, 0, 1, 3], np.int32)
