@@ -50,6 +50,8 @@ def parse():
     p.add_argument("--no-tune", action="store_true", help="heuristic tiles instead of the autotuner")
     p.add_argument("--tune-cache", default=None, help="autotune cache file (read, and appended when tuning)")
     p.add_argument("--serve-seconds", type=float, default=20.0, help="config 5: simulated duration")
+    p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                   help="only run 5 plain device copies of MIB MiB (scale for the DRAM byte counters)")
     return p.parse_args()
 
 
@@ -418,6 +420,16 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding of frames "
                                    "and hypotheses is a design note, not part of this build)"}))
         sys.exit(2)
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy << 20
+        a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n, "copies": 5}))
+        return
     worlds = None
     if args.config == 5:
         t = time.perf_counter()

@@ -201,6 +201,22 @@ int pilot_linearize(pilot_ctx *ctx, const pilot_frame *frame, int level,
                     const double *poses, double *H21, double *g6, double *cost,
                     int32_t *nvalid);
 
+/* Geo-anchor lift on the device (supplement, Geo-anchor Construction; the
+ * step before the optimisation): anchor j given at DSM-crop sample
+ * coordinates uv[2j], uv[2j+1] (u along columns, v along rows) becomes
+ *   x = x0 + u gsd,  y = y0 + v gsd,  z = D(u, v)  (bilinear, clamp-to-edge),
+ * and its reference descriptor is the bilinear sample (clamp-to-edge) of the
+ * Hr x Wr x C reference feature map ref_map (channels-last, dtype f32 or bf16)
+ * at (scale (u + 1/2) - 1/2, scale (v + 1/2) - 1/2), i.e. a map with `scale`
+ * pixels per DSM sample and aligned pixel centres.  Values are computed in
+ * FP64 and rounded once to the output dtype (bf16: round-to-nearest-even).
+ * All arrays are device memory; x, y, z may be NULL (e.g. a second pyramid
+ * level reusing the same anchors); ref_out is N x C in the map's dtype.
+ * C in {16, 32, 64, 128, 256}.  Enqueued on the context stream. */
+int pilot_lift(pilot_ctx *ctx, const float *dsm, int32_t Hd, int32_t Wd, double x0, double y0,
+               double gsd, const float *uv, int32_t N, const void *ref_map, int32_t Hr, int32_t Wr,
+               int32_t C, int32_t dtype, double scale, float *x, float *y, float *z, void *ref_out);
+
 /* ---------------------------------------------------------------------
  * Serving (continuous batching).  A frame is admitted into a slot when a
  * slot and HBM budget are free; pilot_step advances every active slot by

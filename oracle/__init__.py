@@ -90,6 +90,8 @@ def lib():
         L.orc_solve.argtypes = [C.POINTER(_Frame), _dp, C.c_int, C.c_int, _dp, _dp, _ip, _ip, _dp, C.c_int]
         L.orc_best.argtypes = [_dp, _ip, C.c_int]
         L.orc_best.restype = C.c_int
+        L.orc_lift.argtypes = [_dp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, _dp, C.c_int,
+                               _dp, C.c_int, C.c_int, C.c_int, C.c_double, _dp, _dp]
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_get_threads.restype = C.c_int
         _lib = L
@@ -263,6 +265,20 @@ def solve(frame, hyps=None, threads=None, trace=False, of: OracleFrame = None):
     if trace:
         res["trace"] = tr
     return res
+
+
+def lift(dsm, x0, y0, gsd, uv, ref_map, scale):
+    """Anchors (N, 3) and reference descriptors (N, C) lifted from DSM-crop
+    sample coordinates uv (N, 2)."""
+    dsm, uv, ref_map = _f64(dsm), _f64(uv), _f64(ref_map)
+    Hd, Wd = dsm.shape
+    Hr, Wr, Cc = ref_map.shape
+    N = uv.shape[0]
+    P = np.zeros((N, 3))
+    ref = np.zeros((N, Cc))
+    lib().orc_lift(_p(dsm.reshape(-1)), Hd, Wd, float(x0), float(y0), float(gsd), _p(uv.reshape(-1)), N,
+                   _p(ref_map.reshape(-1)), Hr, Wr, Cc, float(scale), _p(P), _p(ref))
+    return P, ref
 
 
 def threads():

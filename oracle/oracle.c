@@ -588,6 +588,32 @@ void orc_solve(const orc_frame *f, const double *poses_in, int m0, int m1,
     free(st);
 }
 
+/* Bilinear sample with clamp-to-edge of a channels-last map at (u, v). */
+static void sample_clamped(const double *F, int H, int W, int C, double u, double v, double *out)
+{
+    if (!(u >= 0.0)) u = 0.0;
+    if (u > W - 1.0) u = W - 1.0;
+    if (!(v >= 0.0)) v = 0.0;
+    if (v > H - 1.0) v = H - 1.0;
+    double du[512], dv[512];
+    orc_bilinear(F, H, W, C, u, v, out, du, dv);
+}
+
+void orc_lift(const double *dsm, int Hd, int Wd, double x0, double y0, double gsd,
+              const double *uv, int N, const double *ref_map, int Hr, int Wr, int C, double scale,
+              double *P, double *ref)
+{
+    for (int j = 0; j < N; ++j) {
+        const double u = uv[2 * j], v = uv[2 * j + 1];
+        double h;
+        sample_clamped(dsm, Hd, Wd, 1, u, v, &h);
+        P[3 * j] = x0 + u * gsd;
+        P[3 * j + 1] = y0 + v * gsd;
+        P[3 * j + 2] = h;
+        sample_clamped(ref_map, Hr, Wr, C, scale * (u + 0.5) - 0.5, scale * (v + 0.5) - 0.5, ref + (size_t)j * C);
+    }
+}
+
 /* Selection of the output pose: the hypothesis with the lowest final
  * objective (Method, Multi-Sensor Optimization).  Non-finite costs and
  * degenerate hypotheses never win; ties go to the lowest index. */

@@ -106,6 +106,16 @@ void orc_solve(const orc_frame *f, const double *poses_in, int m0, int m1,
                double *poses_out, double *cost, int *iterations, int *status,
                double *trace, int trace_stride);
 
+/* Geo-anchor lift (supplement, Geo-anchor Construction): anchor j at DSM-crop
+ * sample coordinates (u_j, v_j) becomes P = (x0 + u gsd, y0 + v gsd, D(u, v))
+ * (bilinear, clamp-to-edge), and its reference descriptor is the bilinear
+ * sample (clamp-to-edge) of an Hr x Wr x C reference map at
+ * (scale (u + 1/2) - 1/2, scale (v + 1/2) - 1/2): map pixels cover the crop
+ * with `scale` map pixels per DSM sample, centres aligned. */
+void orc_lift(const double *dsm, int Hd, int Wd, double x0, double y0, double gsd,
+              const double *uv, int N, const double *ref_map, int Hr, int Wr, int C, double scale,
+              double *P, double *ref);
+
 /* lowest finite cost among non-degenerate hypotheses, ties -> lowest index,
  * -1 if none */
 int orc_best(const double *cost, const int *status, int M);

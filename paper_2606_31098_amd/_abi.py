@@ -68,7 +68,7 @@ class Stats(C.Structure):
 EXPORTS = ["pilot_create", "pilot_destroy", "pilot_last_error", "pilot_solve", "pilot_linearize",
            "pilot_admit_cost", "pilot_admit", "pilot_step", "pilot_poll", "pilot_serving_state",
            "pilot_get_stats", "pilot_autotune", "pilot_tile_choice", "pilot_abi_version", "pilot_sizeof",
-           "pilot_sync"]
+           "pilot_sync", "pilot_lift"]
 
 _lib = None
 
@@ -96,6 +96,8 @@ def load(path: str = LIB_PATH):
     L.pilot_poll.argtypes = [_vp, C.c_int]
     L.pilot_serving_state.argtypes = [_vp, P(C.c_int), P(C.c_size_t)]
     L.pilot_sync.argtypes = [_vp]
+    L.pilot_lift.argtypes = [_vp, _vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, _vp, C.c_int32,
+                             _vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double, _vp, _vp, _vp, _vp]
     L.pilot_get_stats.argtypes = [_vp, P(Stats), C.c_int]
     L.pilot_autotune.argtypes = [_vp, P(Frame)]
     L.pilot_tile_choice.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_char_p, C.c_int]

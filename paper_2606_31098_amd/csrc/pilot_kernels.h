@@ -6,9 +6,10 @@
 namespace pilot {
 
 struct TileConfig {
-    int G;      // lanes per anchor = hypotheses per tile (4, 8 or 16)
-    int PPG;    // anchors per lane group per work item
-    int grid;   // persistent grid size (blocks)
+    int G;          // lanes per anchor = hypotheses per tile (4, 8 or 16)
+    int PPG;        // anchors per lane group per work item
+    int grid;       // blocks per CU of a persistent grid (0: one block per item); launch: blocks
+    int variant = 1;    // 1: batch-then-compute loop; 2: software-pipelined loop
 };
 
 // True if a pass kernel exists for (C, dtype, G).
@@ -28,6 +29,11 @@ hipError_t launch_epilogue(const EpilogueArgs &e, hipStream_t s);
 hipError_t launch_init(const FrameDev *frames, int n_frames, int max_M, HypState *hs,
                        PoseEval *pose, int *hlev, int mode, const double *diag_poses,
                        int diag_level, hipStream_t s);
+
+// Geo-anchor lift and reference-descriptor sampling (see pilot_lift).
+hipError_t launch_lift(const float *dsm, int Hd, int Wd, double x0, double y0, double gsd, const float *uv, int N,
+                       const void *ref_map, int Hr, int Wr, int C, int dtype, double scale, float *x, float *y,
+                       float *z, void *ref_out, hipStream_t s);
 
 // Top-K pruning of frames whose hypotheses all finished their pruning level.
 hipError_t launch_prune(const FrameDev *frames, int n_frames, HypState *hs, PoseEval *pose, int *hlev,

@@ -302,6 +302,64 @@ hipError_t launch_prune(const FrameDev *frames, int n_frames, HypState *hs, Pose
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ anchor lift
+__device__ inline double bilinear_clamped(const float *F, const uint16_t *Fb, int H, int W, int C, int c,
+                                          double u, double v)
+{
+    u = fmin(fmax(u, 0.0), W - 1.0);
+    v = fmin(fmax(v, 0.0), H - 1.0);
+    const int x0 = min((int)u, W - 2), y0 = min((int)v, H - 2);
+    const double a = u - x0, b = v - y0;
+    const size_t o = ((size_t)y0 * W + x0) * C + c;
+    auto at = [&](size_t k) -> double {
+        return F ? (double)F[k] : (double)__uint_as_float(((uint32_t)Fb[k]) << 16);
+    };
+    const double f00 = at(o), f10 = at(o + C), f01 = at(o + (size_t)W * C), f11 = at(o + (size_t)W * C + C);
+    const double top = f00 + a * (f10 - f00), bot = f01 + a * (f11 - f01);
+    return top + b * (bot - top);
+}
+
+__device__ inline uint16_t to_bf16_rne(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);   // NaN stays NaN
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// One thread per (anchor, channel); channel 0 also writes the lifted point.
+__global__ __launch_bounds__(256) void lift_kernel(const float *dsm, int Hd, int Wd, double x0, double y0, double gsd,
+                                                    const float *uv, int N, const void *ref_map, int Hr, int Wr, int C,
+                                                    int dtype, double scale, float *x, float *y, float *z, void *ref_out)
+{
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)N * C) return;
+    const int j = (int)(t / C), c = (int)(t - (size_t)j * C);
+    const double u = uv[2 * j], v = uv[2 * j + 1];
+    if (c == 0) {
+        if (x) x[j] = (float)(x0 + u * gsd);
+        if (y) y[j] = (float)(y0 + v * gsd);
+        if (z) z[j] = (float)bilinear_clamped(dsm, nullptr, Hd, Wd, 1, 0, u, v);
+    }
+    const double val = bilinear_clamped(dtype == 0 ? (const float *)ref_map : nullptr,
+                                        dtype == 0 ? nullptr : (const uint16_t *)ref_map, Hr, Wr, C, c,
+                                        scale * (u + 0.5) - 0.5, scale * (v + 0.5) - 0.5);
+    if (dtype == 0)
+        ((float *)ref_out)[t] = (float)val;
+    else
+        ((uint16_t *)ref_out)[t] = to_bf16_rne((float)val);
+}
+
+hipError_t launch_lift(const float *dsm, int Hd, int Wd, double x0, double y0, double gsd, const float *uv, int N,
+                       const void *ref_map, int Hr, int Wr, int C, int dtype, double scale, float *x, float *y,
+                       float *z, void *ref_out, hipStream_t s)
+{
+    const size_t n = (size_t)N * C;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(lift_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dsm, Hd, Wd, x0, y0, gsd, uv, N,
+                       ref_map, Hr, Wr, C, dtype, scale, x, y, z, ref_out);
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize(const FrameDev *frames, int n_frames, const HypState *hs, const int *hlev,
                            hipStream_t s)
 {

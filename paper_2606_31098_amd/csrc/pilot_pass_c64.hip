@@ -1,6 +1,7 @@
-// Pass kernels for C = 64 channels (f32 and bf16; G = 4, 8, 16).
+// Pass kernels for C = 64 channels (f32 and bf16; G = 4, 8, 16; two loop variants).
 #include "pilot_kernels.h"
 #include "pilot_pass.inc"
+#include "pilot_pass2.inc"
 
 namespace pilot {
 PILOT_INSTANTIATE_PASS(64)

@@ -323,7 +323,7 @@ int log2_bucket(int n)
 std::string tune_key(int C, int dtype, int N, int M)
 {
     std::ostringstream o;
-    o << "C" << C << "_d" << dtype << "_N" << log2_bucket(N) << "_M" << log2_bucket(M);
+    o << "C" << C << "_d" << dtype << "_N" << log2_bucket(N) << "_M" << log2_bucket(M) << "_v2";
     return o.str();
 }
 
@@ -460,12 +460,12 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
         if (only_level >= 0 && l != only_level) continue;
         // each frame's tiles depend on its own shape only, so its sums (and
         // results) are the same alone or batched with any other frames
-        std::map<std::array<int, 4>, std::vector<int>> by_class;
+        std::map<std::array<int, 5>, std::vector<int>> by_class;
         for (int i = 0; i < n; ++i)
             if (l < frames[i].n_levels) {
                 const pilot_level &L = frames[i].level[l];
                 const TileConfig tc = choose_tile(ctx, L.C, L.dtype, L.N, frames[i].M);
-                by_class[{L.C, L.dtype, tc.G, tc.PPG}].push_back(i);
+                by_class[{L.C, L.dtype, tc.G, tc.PPG, tc.variant}].push_back(i);
             }
         for (auto &kv : by_class) {
             LaunchGroup g;
@@ -495,7 +495,7 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
             plan.partial_floats = std::max(plan.partial_floats, (size_t)g.n_items * g.tc.G * kNV);
             plan.groups.push_back(g);
             key << "|l" << l << "c" << g.C << "d" << g.dtype << "G" << g.tc.G << "p" << g.tc.PPG << "g" << g.tc.grid
-                << "i" << g.n_items << "t" << g.n_tiles << "s" << g.passes;
+                << "v" << g.tc.variant << "i" << g.n_items << "t" << g.n_tiles << "s" << g.passes;
         }
     }
     plan.key = key.str();
@@ -632,8 +632,9 @@ void load_tune_cache(pilot_ctx *ctx)
     std::ifstream in(ctx->tune_cache);
     std::string key;
     TileConfig tc;
-    while (in >> key >> tc.G >> tc.PPG >> tc.grid)
-        if (pass_supported(16, 0, tc.G) && tc.PPG >= 1 && tc.PPG <= 64) ctx->tuned[key] = tc;
+    while (in >> key >> tc.G >> tc.PPG >> tc.grid >> tc.variant)
+        if (pass_supported(16, 0, tc.G) && tc.PPG >= 1 && tc.PPG <= 64 && (tc.variant == 1 || tc.variant == 2))
+            ctx->tuned[key] = tc;
 }
 
 int collect_timings(pilot_ctx *ctx)
@@ -842,6 +843,32 @@ int pilot_linearize(pilot_ctx *ctx, const pilot_frame *frame, int level, const d
     return PILOT_OK;
 }
 
+int pilot_lift(pilot_ctx *ctx, const float *dsm, int32_t Hd, int32_t Wd, double x0, double y0, double gsd,
+               const float *uv, int32_t N, const void *ref_map, int32_t Hr, int32_t Wr, int32_t C, int32_t dtype,
+               double scale, float *x, float *y, float *z, void *ref_out)
+{
+    if (!ctx) return fail(nullptr, PILOT_EINVAL, "ctx: NULL");
+    ctx->err.clear();
+    if (N < 0) return fail(ctx, PILOT_EINVAL, "N: must be >= 0");
+    if (N == 0) return PILOT_OK;
+    if (!dsm || Hd < 2 || Wd < 2) return fail(ctx, PILOT_EINVAL, "dsm/Hd/Wd: need a device raster of at least 2x2");
+    if (!(gsd > 0) || !std::isfinite(gsd) || !std::isfinite(x0) || !std::isfinite(y0))
+        return fail(ctx, PILOT_EINVAL, "x0/y0/gsd: invalid");
+    if (!uv) return fail(ctx, PILOT_EINVAL, "uv: NULL");
+    if (!ref_map || Hr < 2 || Wr < 2) return fail(ctx, PILOT_EINVAL, "ref_map/Hr/Wr: need a device map of at least 2x2");
+    if (C != 16 && C != 32 && C != 64 && C != 128 && C != 256)
+        return fail(ctx, PILOT_EINVAL, "C: must be 16, 32, 64, 128 or 256 (got %d)", C);
+    if (dtype != PILOT_F32 && dtype != PILOT_BF16) return fail(ctx, PILOT_EINVAL, "dtype: must be PILOT_F32 or PILOT_BF16");
+    if (!(scale > 0) || !std::isfinite(scale)) return fail(ctx, PILOT_EINVAL, "scale: must be finite and > 0");
+    if (!ref_out) return fail(ctx, PILOT_EINVAL, "ref_out: NULL");
+    if ((double)Hr * Wr * C >= 2147483647.0 || (double)N * C >= 2147483647.0)
+        return fail(ctx, PILOT_EINVAL, "Hr*Wr*C and N*C must be < 2^31");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, launch_lift(dsm, Hd, Wd, x0, y0, gsd, uv, N, ref_map, Hr, Wr, C, dtype, scale, x, y, z, ref_out,
+                            ctx->stream));
+    return PILOT_OK;
+}
+
 int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
 {
     if (!ctx) return fail(nullptr, PILOT_EINVAL, "ctx: NULL");
@@ -855,11 +882,12 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
         if (ctx->tuned.count(key)) continue;
         TileConfig best{};
         float best_ms = 1e30f;
+        for (int variant : {1, 2})
         for (int G : {4, 8, 16}) {
             if (L.C / G < 1) continue;
             for (int ppg : {2, 4, 8, 16}) {
                 for (int bpc : {0, 2, 4}) {
-                    TileConfig tc{G, ppg, bpc};
+                    TileConfig tc{G, ppg, bpc, variant};
                     ctx->tuned[key] = tc;
                     Plan plan;
                     build_plan(ctx, frame, 1, nullptr, l, plan);
@@ -898,7 +926,7 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
         ctx->tuned[key] = best;
         if (!ctx->tune_cache.empty()) {
             std::ofstream out(ctx->tune_cache, std::ios::app);
-            out << key << " " << best.G << " " << best.PPG << " " << best.grid << "\n";
+            out << key << " " << best.G << " " << best.PPG << " " << best.grid << " " << best.variant << "\n";
         }
     }
     return PILOT_OK;
@@ -908,7 +936,7 @@ int pilot_tile_choice(pilot_ctx *ctx, int C, int dtype, int N, int M, char *buf,
 {
     if (!ctx || !buf || buflen < 1) return fail(ctx, PILOT_EINVAL, "ctx/buf: invalid");
     TileConfig tc = choose_tile(ctx, C, dtype, N, M);
-    snprintf(buf, buflen, "G=%d PPG=%d BPC=%d tuned=%d", tc.G, tc.PPG, tc.grid,
+    snprintf(buf, buflen, "G=%d PPG=%d BPC=%d V=%d tuned=%d", tc.G, tc.PPG, tc.grid, tc.variant,
              (int)ctx->tuned.count(tune_key(C, dtype, N, M)));
     return PILOT_OK;
 }
@@ -1040,12 +1068,12 @@ int serving_rebuild(pilot_ctx *ctx)
             slot_of.push_back(i);
         }
     for (int l = 0; l < PILOT_MAX_LEVELS; ++l) {
-        std::map<std::array<int, 4>, std::vector<int>> by_class;
+        std::map<std::array<int, 5>, std::vector<int>> by_class;
         for (int k = 0; k < (int)frames.size(); ++k)
             if (l < frames[k].n_levels) {
                 const pilot_level &L = frames[k].level[l];
                 const TileConfig tc = choose_tile(ctx, L.C, L.dtype, L.N, frames[k].M);
-                by_class[{L.C, L.dtype, tc.G, tc.PPG}].push_back(k);
+                by_class[{L.C, L.dtype, tc.G, tc.PPG, tc.variant}].push_back(k);
             }
         for (auto &kv : by_class) {
             LaunchGroup g;

@@ -205,6 +205,27 @@ class Context:
                                              g.data_ptr(), cost.data_ptr(), n.data_ptr()))
         return H, g, cost, n
 
+    def lift(self, dsm: torch.Tensor, x0: float, y0: float, gsd: float, uv: torch.Tensor, ref_map: torch.Tensor,
+             scale: float, points: bool = True):
+        """Lift anchors at DSM-crop coordinates uv (N, 2) and sample their
+        reference descriptors from ref_map (Hr, Wr, C; f32 or bf16).
+        Returns (x, y, z, ref) device tensors (x, y, z None if points=False)."""
+        dsm = dsm.to(torch.float32).contiguous()
+        uv = uv.to(torch.float32).contiguous()
+        ref_map = ref_map.contiguous()
+        N = int(uv.shape[0])
+        Hr, Wr, Cc = ref_map.shape
+        dt = A.BF16 if ref_map.dtype == torch.bfloat16 else A.F32
+        dev = uv.device
+        x = y = z = None
+        if points:
+            x, y, z = [torch.empty(N, dtype=torch.float32, device=dev) for _ in range(3)]
+        ref = torch.empty((N, Cc), dtype=ref_map.dtype, device=dev)
+        self._check(self.lib.pilot_lift(self.h, dsm.data_ptr(), dsm.shape[0], dsm.shape[1], float(x0), float(y0),
+                                        float(gsd), uv.data_ptr(), N, ref_map.data_ptr(), Hr, Wr, Cc, dt,
+                                        float(scale), _ptr(x), _ptr(y), _ptr(z), ref.data_ptr()))
+        return x, y, z, ref
+
     def autotune(self, frame: DeviceFrame):
         self._check(self.lib.pilot_autotune(self.h, C.byref(frame.s)))
 

@@ -72,6 +72,8 @@ def test_null_arguments_are_rejected_without_a_device(lib):
     assert L.pilot_create(C.byref(h), None) == A.EINVAL
     assert h.value is None
     assert L.pilot_solve(None, None, 0, None) == A.EINVAL
+    assert L.pilot_lift(None, None, 2, 2, 0.0, 0.0, 1.0, None, 1, None, 2, 2, 32, A.F32, 1.0,
+                        None, None, None, None) == A.EINVAL
     L.pilot_destroy(None)
 
 

@@ -247,3 +247,42 @@ def test_query_confidence_weights_match_oracle():
             err = rel_frobenius(np.concatenate([H[m], g[m][:, None]], 1), np.concatenate([Ho, go[:, None]], 1))
             assert err <= 1e-5, (lvl, m, err)
             assert abs(cost[m] - co) <= 1e-9 * abs(co), (lvl, m, cost[m], co)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_device_lift_matches_oracle(dtype):
+    """pilot_lift against the oracle's lift: points to f32 rounding, the
+    descriptors to the rounding of the output dtype."""
+    from paper_2606_31098_amd.pilot import Context
+    rng = np.random.default_rng(17)
+    D = rng.uniform(0, 50, size=(37, 45)).astype(np.float32)
+    Hr, Wr, Cc, sc = 74, 90, 32, 2.0
+    Fm = rng.normal(size=(Hr, Wr, Cc)).astype(np.float32)
+    if dtype == "bf16":
+        Fm = torch.as_tensor(Fm).to(torch.bfloat16).float().numpy()
+    uv = np.concatenate([rng.uniform(-1, 46, size=(500, 1)), rng.uniform(-1, 38, size=(500, 1))], 1).astype(np.float32)
+    P, ref = oracle.lift(D, -11.0, 4.5, 0.5, uv.astype(np.float64), Fm, sc)
+    ctx = Context(0)
+    tmap = torch.as_tensor(Fm, device="cuda")
+    if dtype == "bf16":
+        tmap = tmap.to(torch.bfloat16)
+    x, y, z, r = ctx.lift(torch.as_tensor(D, device="cuda"), -11.0, 4.5, 0.5, torch.as_tensor(uv, device="cuda"),
+                          tmap, sc)
+    torch.cuda.synchronize()
+    got = np.stack([x.cpu().numpy(), y.cpu().numpy(), z.cpu().numpy()], 1)
+
+    def within_ulp(a, b):       # FP64 sums in another order may round to the neighbouring f32
+        b32 = b.astype(np.float32)
+        return bool(np.all(np.abs(a.astype(np.float64) - b32) <= np.spacing(np.abs(b32)).astype(np.float64)))
+
+    assert within_ulp(got, P)
+    expect = torch.as_tensor(ref).float()
+    if dtype == "bf16":
+        expect = expect.to(torch.bfloat16)
+    gr = r.cpu()
+    if dtype == "f32":
+        assert within_ulp(gr.numpy(), ref)
+    else:
+        gi = gr.view(torch.int16).numpy().astype(np.int32)
+        ei = expect.view(torch.int16).numpy().astype(np.int32)
+        assert np.abs(gi - ei).max() <= 1                 # one bf16 ulp (double rounding f64 -> f32 -> bf16)

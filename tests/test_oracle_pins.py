@@ -384,6 +384,28 @@ def test_top_k_pruning_keeps_the_lowest_post_coarse_costs():
     assert r["best"] in expect
 
 
+def test_lift_at_grid_points_and_affine_maps():
+    """Anchors at integer DSM samples lift to the raster's own heights and
+    coordinates; an affine reference map is reproduced exactly, clamped at
+    the border."""
+    rng = np.random.default_rng(12)
+    D = rng.uniform(0, 50, size=(9, 11))
+    uv = np.array([[0, 0], [10, 8], [3, 4], [2.5, 7.25], [-3.0, 1.0], [10.7, 8.9]])
+    Hr, Wr, Cc, sc = 18, 22, 3, 2.0
+    a, b, c = rng.normal(size=Cc), rng.normal(size=Cc), rng.normal(size=Cc)
+    vv, uu = np.mgrid[0:Hr, 0:Wr]
+    Fm = uu[..., None] * a + vv[..., None] * b + c
+    P, ref = oracle.lift(D, -5.0, 7.0, 0.5, uv, Fm, sc)
+    for k in range(3):
+        u, v = uv[k].astype(int)
+        assert P[k, 2] == D[v, u] and P[k, 0] == -5.0 + 0.5 * u and P[k, 1] == 7.0 + 0.5 * v
+    for k in range(len(uv)):
+        mu = np.clip(sc * (uv[k, 0] + 0.5) - 0.5, 0, Wr - 1)
+        mv = np.clip(sc * (uv[k, 1] + 0.5) - 0.5, 0, Hr - 1)
+        assert np.allclose(ref[k], a * mu + b * mv + c, atol=1e-12)
+    assert P[4, 2] == pytest.approx(D[1, 0])        # clamped in u
+
+
 def test_selection_rule():
     cost = np.array([3.0, np.nan, 1.0, 1.0, 0.5])
     st = np.array([1, 1, 0, 1, 3], np.int32)
