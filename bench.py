@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "point-residual evals/s (GB/s vs HBM peak); p50/p99 frame latency, BF16 vs FP32"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_kernel_traffic.json")
+TILES_FILE = os.path.join(ROOT, "paper_2606_31098_amd", "tiles_gfx950.txt")
 
 
 def parse():
@@ -48,7 +49,10 @@ def parse():
     p.add_argument("--no-bf16", action="store_true", help="config 2: skip the bf16 comparison")
     p.add_argument("--frame-seed", type=int, default=0)
     p.add_argument("--no-tune", action="store_true", help="heuristic tiles instead of the autotuner")
-    p.add_argument("--tune-cache", default=None, help="autotune cache file (read, and appended when tuning)")
+    p.add_argument("--tune-cache", default=TILES_FILE,
+                   help="tile database (read; shapes missing from it are tuned and appended)")
+    p.add_argument("--write-tiles", action="store_true",
+                   help="only tune the tiles of every workload shape into --tune-cache")
     p.add_argument("--serve-seconds", type=float, default=20.0, help="config 5: simulated duration")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="only run 5 plain device copies of MIB MiB (scale for the DRAM byte counters)")
@@ -167,7 +171,7 @@ def cpu_leg(args, frames):
     t0 = time.perf_counter()
     oracle.solve(f, hyps=[0], threads=1)
     t1 = time.perf_counter() - t0
-    th = oracle.threads()
+    th = oracle.threads(0)
     k = int(max(1, min(f.M, args.cpu_seconds / max(t1, 1e-3) * th)))
     hyps = np.arange(k)
     t0 = time.perf_counter()
@@ -191,6 +195,37 @@ def line(args, value, steps, warmup, ms, dtype, workload, extra):
 
 
 # ------------------------------------------------------------------ configs
+def config_frames(cfg, seed):
+    from synth import frames as S
+    if cfg == 4:
+        return S.make_batch(64, field_pool=4), "bf16"
+    if cfg == 0:
+        return [S.paper_shaped_frame(seed)], "f32"
+    return [S.make_frame(cfg, seed)], ("bf16" if cfg == 3 else "f32")
+
+
+def write_tiles(args):
+    """Tune the pass-kernel tiles of every workload shape (solve configs,
+    config 2 in bf16, the serving shapes) into the tile database."""
+    import torch
+
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    from synth import frames as S
+    from synth import sequences as Q
+    ctx = Context(0, tune_cache=args.tune_cache)
+    sets = [(c,) + config_frames(c, 0) for c in (0, 1, 2, 3, 4)]
+    sets.append((2, config_frames(2, 0)[0], "bf16"))
+    serve = [S.make_frame(2, 0, N=side * side // 32, M=m, level_shapes=Q.LEVELS, iters=Q.ITERS, dsm_side=side)
+             for side in (128, 256, 512) for m in (64, 128, 256, 512)]
+    sets.append(("serving", serve, "bf16"))
+    for name, frames, dtype in sets:
+        t = time.perf_counter()
+        tune(ctx, args, [DeviceFrame(f, dtype=dtype) for f in frames])
+        torch.cuda.synchronize()
+        log(f"tiles of {name} {dtype}: {time.perf_counter() - t:.1f} s")
+    ctx.close()
+
+
 def run_solve_config(args):
     import numpy as np
     import torch
@@ -200,15 +235,7 @@ def run_solve_config(args):
 
     cfg = args.config
     t = time.perf_counter()
-    if cfg == 4:
-        frames = S.make_batch(64, field_pool=4)
-        dtype = "bf16"
-    elif cfg == 0:
-        frames = [S.paper_shaped_frame(args.frame_seed)]
-        dtype = "f32"
-    else:
-        frames = [S.make_frame(cfg, args.frame_seed)]
-        dtype = "bf16" if cfg == 3 else "f32"
+    frames, dtype = config_frames(cfg, args.frame_seed)
     log(f"generated {len(frames)} frame(s) in {time.perf_counter() - t:.1f}s")
     dfs = [DeviceFrame(f, dtype=dtype) for f in frames]
     torch.cuda.synchronize()
@@ -306,7 +333,7 @@ def run_serving_config(args, worlds):
     dsm_dev = [torch.as_tensor(w.dsm.heights, device=dev) for w in worlds]
     torch.cuda.synchronize()
     budget = 24 << 30
-    ctx = Context(0, max_slots=48, hbm_budget_bytes=budget)
+    ctx = Context(0, max_slots=48, hbm_budget_bytes=budget, tune_cache=args.tune_cache)
     lm = dict(S.LM_DEFAULTS)
     counter = [0]
     best_poses = torch.empty((n_frames, 12), dtype=torch.float64, device=dev)
@@ -429,6 +456,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": n, "copies": 5}))
+        return
+    if args.write_tiles:
+        write_tiles(args)
         return
     worlds = None
     if args.config == 5:

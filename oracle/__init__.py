@@ -47,7 +47,9 @@ class _Frame(C.Structure):
                 ("tau", C.c_double), ("up", C.c_double), ("down", C.c_double),
                 ("lam_min_rel", C.c_double), ("lam_max_rel", C.c_double),
                 ("tol_t", C.c_double), ("tol_r", C.c_double), ("z_min", C.c_double),
-                ("min_valid", C.c_int), ("keep_top", C.c_int), ("prune_level", C.c_int)]
+                ("min_valid", C.c_int), ("keep_top", C.c_int), ("prune_level", C.c_int),
+                ("adaptive", C.c_int), ("alpha_ratio", C.c_double), ("grav_gate", C.c_double),
+                ("range_gate", C.c_double)]
 
 
 def build(force: bool = True) -> str:
@@ -87,7 +89,12 @@ def lib():
         L.orc_linearize.argtypes = [C.POINTER(_Frame), C.c_int, _dp, _dp, _dp, _dp, _ip]
         L.orc_cholesky_solve6.argtypes = [_dp, _dp, _dp]
         L.orc_cholesky_solve6.restype = C.c_int
+        L.orc_linearize_visual.argtypes = [C.POINTER(_Frame), C.c_int, _dp, _dp, _dp, _dp, _ip]
+        L.orc_add_priors.argtypes = [C.POINTER(_Frame), _dp, C.c_double, C.c_double, _dp, _dp, _dp]
+        L.orc_prior_scales.argtypes = [C.POINTER(_Frame), _dp, _dp, _dp]
         L.orc_solve.argtypes = [C.POINTER(_Frame), _dp, C.c_int, C.c_int, _dp, _dp, _ip, _ip, _dp, C.c_int]
+        L.orc_solve_alpha.argtypes = [C.POINTER(_Frame), _dp, C.c_int, C.c_int, _dp, _dp, _ip, _ip, _dp, C.c_int,
+                                      _dp]
         L.orc_best.argtypes = [_dp, _ip, C.c_int]
         L.orc_best.restype = C.c_int
         L.orc_lift.argtypes = [_dp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, _dp, C.c_int,
@@ -155,6 +162,10 @@ class OracleFrame:
         s.min_valid = int(lm["min_valid"])
         s.keep_top = int(getattr(frame, "keep_top", 0))
         s.prune_level = int(getattr(frame, "prune_level", 0))
+        s.adaptive = int(getattr(frame, "adaptive_priors", 0))
+        s.alpha_ratio = float(getattr(frame, "alpha_ratio", 0.0))
+        s.grav_gate = float(getattr(frame, "gravity_gate", 0.0))
+        s.range_gate = float(getattr(frame, "range_gate", 0.0))
         self.s = s
         self.ptr = C.pointer(s)
 
@@ -230,6 +241,19 @@ def linearize(of: OracleFrame, level, T):
     return H.reshape(6, 6), g, c.value, n.value
 
 
+def linearize_visual(of: OracleFrame, level, T):
+    H, g = np.zeros(36), np.zeros(6)
+    c, n = C.c_double(), C.c_int()
+    lib().orc_linearize_visual(of.ptr, level, _p(_f64(T)), _p(H), _p(g), C.byref(c), C.byref(n))
+    return H.reshape(6, 6), g, c.value, n.value
+
+
+def prior_scales(of: OracleFrame, T, g_vis):
+    a = np.zeros(2)
+    lib().orc_prior_scales(of.ptr, _p(_f64(T)), _p(_f64(g_vis)), _p(a))
+    return a
+
+
 def cholesky_solve6(A, b):
     x = np.zeros(6)
     rc = lib().orc_cholesky_solve6(_p(_f64(A).reshape(-1)), _p(_f64(b)), _p(x))
@@ -241,6 +265,7 @@ def solve(frame, hyps=None, threads=None, trace=False, of: OracleFrame = None):
     top-K pruning the ranking is among the solved hypotheses).
 
     Returns dict with poses (k,12), cost (k), iterations (k), status (k),
+    alpha (k, 2: gravity and range scales of the last level started),
     best (index into the full hypothesis set among the solved ones, or -1)
     and, with trace=True, trace (k, rows, 4)."""
     of = of or OracleFrame(frame)
@@ -257,10 +282,11 @@ def solve(frame, hyps=None, threads=None, trace=False, of: OracleFrame = None):
     tr = np.zeros((k, max(rows, 1), 4)) if trace else None
     L = lib()
     L.orc_set_threads(int(threads) if threads else 0)          # 0: all OpenMP threads
-    L.orc_solve(of.ptr, _p(sub), 0, k, _p(out), _p(cost), its.ctypes.data_as(_ip),
-                st.ctypes.data_as(_ip), _p(tr) if trace else _dp(), max(rows, 1))
+    alpha = np.zeros((k, 2))
+    L.orc_solve_alpha(of.ptr, _p(sub), 0, k, _p(out), _p(cost), its.ctypes.data_as(_ip),
+                      st.ctypes.data_as(_ip), _p(tr) if trace else _dp(), max(rows, 1), _p(alpha))
     b = L.orc_best(_p(cost), st.ctypes.data_as(_ip), k)
-    res = dict(poses=out, cost=cost, iterations=its, status=st,
+    res = dict(poses=out, cost=cost, iterations=its, status=st, alpha=alpha,
                best=int(idx[b]) if b >= 0 else -1, index=idx)
     if trace:
         res["trace"] = tr
@@ -281,5 +307,8 @@ def lift(dsm, x0, y0, gsd, uv, ref_map, scale):
     return P, ref
 
 
-def threads():
+def threads(n=None):
+    """Threads the oracle's solve uses; with n, set them first (0 = all)."""
+    if n is not None:
+        lib().orc_set_threads(int(n))
     return lib().orc_get_threads()

@@ -356,8 +356,8 @@ void orc_range(const orc_frame *f, const double T[12], double *r, double J[6])
 /* W holds the IRLS weight rho'(s) times the confidence w, s = w |r|^2      */
 /* (Eq. (2)).  Anchors outside the view add the constant rho(2 w_ref).      */
 /* ------------------------------------------------------------------ */
-void orc_linearize(const orc_frame *f, int l, const double T[12],
-                   double H[36], double g[6], double *cost, int *nvalid)
+void orc_linearize_visual(const orc_frame *f, int l, const double T[12],
+                          double H[36], double g[6], double *cost, int *nvalid)
 {
     const orc_level *L = &f->lv[l];
     int C = L->C;
@@ -393,13 +393,24 @@ void orc_linearize(const orc_frame *f, int l, const double T[12],
             g[a] += W * sg;
         }
     }
+    *cost = c;
+    *nvalid = n;
+}
+
+/* Gravity and range terms of Eq. (7) with scales a_grav, a_range (the
+ * lambda_imu, lambda_range of Eq. (7); the alpha of the supplement's
+ * H_total, g_total). */
+void orc_add_priors(const orc_frame *f, const double T[12], double a_grav, double a_range,
+                    double H[36], double g[6], double *cost)
+{
+    double c = *cost;
     if (f->use_gravity) {
         double rg[3], Jg[18], rho, drho;
         orc_gravity(f, T, rg, Jg);
         double s = rg[0] * rg[0] + rg[1] * rg[1] + rg[2] * rg[2];
         orc_robust(f->grav_loss_kind, f->grav_loss_scale, s, &rho, &drho);
-        c += f->lambda_imu * rho;
-        double W = f->lambda_imu * drho;
+        c += a_grav * rho;
+        double W = a_grav * drho;
         for (int a = 0; a < 6; ++a) {
             for (int b = 0; b < 6; ++b) {
                 double sum = 0.0;
@@ -415,15 +426,72 @@ void orc_linearize(const orc_frame *f, int l, const double T[12],
         double rr, Jr[6], rho, drho;
         orc_range(f, T, &rr, Jr);
         orc_robust(f->range_loss_kind, f->range_loss_scale, rr * rr, &rho, &drho);
-        c += f->lambda_range * rho;
-        double W = f->lambda_range * drho;
+        c += a_range * rho;
+        double W = a_range * drho;
         for (int a = 0; a < 6; ++a) {
             for (int b = 0; b < 6; ++b) H[6 * a + b] += W * Jr[a] * Jr[b];
             g[a] += W * Jr[a] * rr;
         }
     }
     *cost = c;
-    *nvalid = n;
+}
+
+void orc_linearize(const orc_frame *f, int l, const double T[12],
+                   double H[36], double g[6], double *cost, int *nvalid)
+{
+    orc_linearize_visual(f, l, T, H, g, cost, nvalid);
+    orc_add_priors(f, T, f->lambda_imu, f->lambda_range, H, g, cost);
+}
+
+/* One prior's unit-scale gradient norm and residual norm. */
+static void prior_unit(const orc_frame *f, const double T[12], int which, double *gnorm, double *rnorm)
+{
+    double gs[6] = {0, 0, 0, 0, 0, 0};
+    if (which == 0) {
+        double r[3], J[18], rho, drho;
+        orc_gravity(f, T, r, J);
+        const double s = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        orc_robust(f->grav_loss_kind, f->grav_loss_scale, s, &rho, &drho);
+        for (int a = 0; a < 6; ++a)
+            for (int k = 0; k < 3; ++k) gs[a] += J[6 * k + a] * drho * r[k];
+        *rnorm = sqrt(s);
+    } else {
+        double r, J[6], rho, drho;
+        orc_range(f, T, &r, J);
+        orc_robust(f->range_loss_kind, f->range_loss_scale, r * r, &rho, &drho);
+        for (int a = 0; a < 6; ++a) gs[a] = J[a] * drho * r;
+        *rnorm = fabs(r);
+    }
+    double n2 = 0.0;
+    for (int a = 0; a < 6; ++a) n2 += gs[a] * gs[a];
+    *gnorm = sqrt(n2);
+}
+
+/* Adaptive prior scales (supplement, Sensor-Prior Fusion in LM): a prior's
+ * scale shrinks when its gradient would dominate the visual one (relative
+ * gradient magnitudes) and when its residual is implausibly large (the
+ * residual-dependent gate). */
+void orc_prior_scales(const orc_frame *f, const double T[12], const double g_vis[6], double alpha[2])
+{
+    const int use[2] = {f->use_gravity, f->use_range};
+    const double lam[2] = {f->lambda_imu, f->lambda_range};
+    const double gate[2] = {f->grav_gate, f->range_gate};
+    double gv = 0.0;
+    for (int a = 0; a < 6; ++a) gv += g_vis[a] * g_vis[a];
+    gv = sqrt(gv);
+    for (int s = 0; s < 2; ++s) {
+        if (!use[s]) {
+            alpha[s] = 0.0;
+            continue;
+        }
+        alpha[s] = lam[s];
+        if (!f->adaptive) continue;
+        double gn, rn;
+        prior_unit(f, T, s, &gn, &rn);
+        if (f->alpha_ratio > 0.0 && lam[s] * gn > f->alpha_ratio * gv)
+            alpha[s] *= f->alpha_ratio * gv / (lam[s] * gn);
+        if (gate[s] > 0.0 && rn > gate[s]) alpha[s] *= (gate[s] / rn) * (gate[s] / rn);
+    }
 }
 
 /* Damped 6x6 solve of Eq. (8) by Cholesky factorisation A = L L^T. */
@@ -475,15 +543,29 @@ static int all_finite(const double *a, int n)
 typedef struct {
     double T[12];
     double c;
+    double alpha[2];
     int status, total_it, row, finished;
 } hyp_state;
+
+/* objective at level l with the level's frozen prior scales */
+static void linearize_at(const orc_frame *f, int l, const double T[12], const double alpha[2],
+                         double H[36], double g[6], double *cost, int *nvalid)
+{
+    orc_linearize_visual(f, l, T, H, g, cost, nvalid);
+    orc_add_priors(f, T, alpha[0], alpha[1], H, g, cost);
+}
 
 /* One level of LM for one hypothesis. */
 static void run_level(const orc_frame *f, int l, hyp_state *st, double *trace, int trace_stride)
 {
     double H[36], g[6], c;
     int n;
-    orc_linearize(f, l, st->T, H, g, &c, &n);
+    /* the scales are chosen once at the level's starting pose and held for
+     * the level, so the level's objective is fixed and a decrease of the cost
+     * is well defined */
+    orc_linearize_visual(f, l, st->T, H, g, &c, &n);
+    orc_prior_scales(f, st->T, g, st->alpha);
+    orc_add_priors(f, st->T, st->alpha[0], st->alpha[1], H, g, &c);
     st->c = c;
     double D = 0.0;
     for (int i = 0; i < 6; ++i)
@@ -515,7 +597,7 @@ static void run_level(const orc_frame *f, int l, hyp_state *st, double *trace, i
         int nc;
         orc_exp(dx, E);
         orc_compose(E, st->T, Tc);
-        orc_linearize(f, l, Tc, Hc, gc, &cc, &nc);
+        linearize_at(f, l, Tc, st->alpha, Hc, gc, &cc, &nc);
         if (tr) { tr[0] = l; tr[1] = c; tr[2] = cc; tr[3] = 0; }
         if (cc < c) {
             if (tr) tr[3] = 1;
@@ -540,6 +622,13 @@ static void run_level(const orc_frame *f, int l, hyp_state *st, double *trace, i
 void orc_solve(const orc_frame *f, const double *poses_in, int m0, int m1,
                double *poses_out, double *cost, int *iterations, int *status,
                double *trace, int trace_stride)
+{
+    orc_solve_alpha(f, poses_in, m0, m1, poses_out, cost, iterations, status, trace, trace_stride, NULL);
+}
+
+void orc_solve_alpha(const orc_frame *f, const double *poses_in, int m0, int m1,
+                     double *poses_out, double *cost, int *iterations, int *status,
+                     double *trace, int trace_stride, double *alpha)
 {
     const int k = m1 - m0;
     if (trace)
@@ -584,6 +673,10 @@ void orc_solve(const orc_frame *f, const double *poses_in, int m0, int m1,
         cost[m0 + i] = st[i].c;
         iterations[m0 + i] = st[i].total_it;
         status[m0 + i] = st[i].status;
+        if (alpha) {
+            alpha[2 * (m0 + i)] = st[i].alpha[0];
+            alpha[2 * (m0 + i) + 1] = st[i].alpha[1];
+        }
     }
     free(st);
 }

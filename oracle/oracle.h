@@ -60,6 +60,13 @@ typedef struct {
      * prune_level every hypothesis has finished that level; only the keep_top
      * lowest costs continue (0 = no pruning) */
     int keep_top, prune_level;
+    /* adaptive prior scales (supplement, Sensor-Prior Fusion in LM): when
+     * adaptive != 0 the scales of the gravity and range terms are set at the
+     * start of every level from the relative gradient magnitudes (cap ratio
+     * alpha_ratio) and residual gates (grav_gate, range_gate), then held for
+     * that level; see orc_prior_scales */
+    int adaptive;
+    double alpha_ratio, grav_gate, range_gate;
 } orc_frame;
 
 /* SE(3) */
@@ -89,10 +96,30 @@ void orc_gravity(const orc_frame *f, const double T[12], double r[3], double J[1
 /* laser-range residual and Jacobian (1*6) */
 void orc_range(const orc_frame *f, const double T[12], double *r, double J[6]);
 
-/* total objective at level l and its Gauss-Newton system:
+/* total objective at level l and its Gauss-Newton system with the fixed
+ * prior scales lambda_imu, lambda_range:
  * H (6*6), g (6) = J^T W r, cost, number of visible anchors */
 void orc_linearize(const orc_frame *f, int l, const double T[12],
                    double H[36], double g[6], double *cost, int *nvalid);
+
+/* the visual term alone (photo residuals and out-of-view penalties) */
+void orc_linearize_visual(const orc_frame *f, int l, const double T[12],
+                          double H[36], double g[6], double *cost, int *nvalid);
+
+/* add the gravity and range terms (those enabled) with scales a_grav,
+ * a_range to H, g, cost */
+void orc_add_priors(const orc_frame *f, const double T[12], double a_grav, double a_range,
+                    double H[36], double g[6], double *cost);
+
+/* Adaptive prior scales at pose T given the visual gradient g_vis:
+ * for each enabled prior s with base scale lambda_s, unit-scale gradient
+ * g_s = J_s^T rho_s' r_s and residual norm |r_s|,
+ *   alpha_s = lambda_s * min(1, alpha_ratio |g_vis| / (lambda_s |g_s|))
+ *                      * min(1, (gate_s / |r_s|)^2),
+ * where a factor is 1 when its parameter is <= 0 (or |g_s| = 0).  A
+ * disabled prior gets 0.  With adaptive == 0: alpha = (lambda_imu,
+ * lambda_range) of the enabled priors. */
+void orc_prior_scales(const orc_frame *f, const double T[12], const double g_vis[6], double alpha[2]);
 
 /* (A) x = b for a 6x6 SPD A by Cholesky; returns 0, or -1 if not PD */
 int orc_cholesky_solve6(const double A[36], const double b[6], double x[6]);
@@ -105,6 +132,12 @@ int orc_cholesky_solve6(const double A[36], const double b[6], double x[6]);
 void orc_solve(const orc_frame *f, const double *poses_in, int m0, int m1,
                double *poses_out, double *cost, int *iterations, int *status,
                double *trace, int trace_stride);
+
+/* the prior scales (gravity, range) each hypothesis used at the last level it
+ * started, indexed by m, after orc_solve_alpha's run (alpha: M*2) */
+void orc_solve_alpha(const orc_frame *f, const double *poses_in, int m0, int m1,
+                     double *poses_out, double *cost, int *iterations, int *status,
+                     double *trace, int trace_stride, double *alpha);
 
 /* Geo-anchor lift (supplement, Geo-anchor Construction): anchor j at DSM-crop
  * sample coordinates (u_j, v_j) becomes P = (x0 + u gsd, y0 + v gsd, D(u, v))

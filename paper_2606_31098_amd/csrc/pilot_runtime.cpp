@@ -330,7 +330,7 @@ std::string tune_key(int C, int dtype, int N, int M)
 TileConfig heuristic_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M)
 {
     TileConfig tc;
-    tc.G = (C == 16) ? 4 : 8;
+    tc.G = (C >= 128) ? 8 : 4;      // measured: G = 4 up to C = 64, G = 8 at C = 128
     const int NG = kBlock / tc.G;
     const long ht = (M + tc.G - 1) / tc.G;
     tc.PPG = 1;
@@ -869,6 +869,38 @@ int pilot_lift(pilot_ctx *ctx, const float *dsm, int32_t Hd, int32_t Wd, double 
     return PILOT_OK;
 }
 
+// One eager solve of `frame` with per-pass events; summed pass-kernel ms per
+// level into ms[].  The context's counters are left as they were.
+static int timed_solve(pilot_ctx *ctx, const pilot_frame *frame, const pilot_result *res, double ms[PILOT_MAX_LEVELS])
+{
+    Plan plan;
+    build_plan(ctx, frame, 1, res, -1, plan);
+    int rc = ensure_state(ctx, plan);
+    if (rc) return rc;
+    DevPtrs dp;
+    if ((rc = upload_plan(ctx, plan, dp))) return rc;
+    uint64_t launches[kStatClasses];
+    memcpy(launches, ctx->launches, sizeof launches);
+    rc = enqueue_schedule(ctx, plan, dp, ctx->stream, true);
+    memcpy(ctx->launches, launches, sizeof launches);
+    if (rc) return rc;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int l = 0; l < PILOT_MAX_LEVELS; ++l) ms[l] = 0.0;
+    for (TimedLaunch &t : ctx->timed) {
+        float x = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&x, t.a, t.b));
+        ms[t.level] += x;
+        ctx->event_pool.push_back(t.a);
+        ctx->event_pool.push_back(t.b);
+    }
+    ctx->timed.clear();
+    return PILOT_OK;
+}
+
+// Tiles are chosen by what they cost inside a solve of the caller's frame:
+// hypotheses finish at different iterations, and a tile is paid for as
+// long as any of its hypotheses is active, so timing a pass with every
+// hypothesis active favours tiles that are slower in practice.
 int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
 {
     if (!ctx) return fail(nullptr, PILOT_EINVAL, "ctx: NULL");
@@ -876,57 +908,104 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
     if (rc) return rc;
     if (ctx->n_active() > 0) return fail(ctx, PILOT_EINVAL, "context has active serving slots");
     HIPCHK(ctx, hipSetDevice(ctx->device));
+    std::vector<std::string> keys(frame->n_levels);
+    std::vector<std::string> todo;
     for (int l = 0; l < frame->n_levels; ++l) {
         const pilot_level &L = frame->level[l];
-        const std::string key = tune_key(L.C, L.dtype, L.N, frame->M);
-        if (ctx->tuned.count(key)) continue;
-        TileConfig best{};
-        float best_ms = 1e30f;
-        for (int variant : {1, 2})
-        for (int G : {4, 8, 16}) {
-            if (L.C / G < 1) continue;
-            for (int ppg : {2, 4, 8, 16}) {
-                for (int bpc : {0, 2, 4}) {
-                    TileConfig tc{G, ppg, bpc, variant};
-                    ctx->tuned[key] = tc;
-                    Plan plan;
-                    build_plan(ctx, frame, 1, nullptr, l, plan);
-                    if ((rc = ensure_state(ctx, plan))) return rc;
-                    DevPtrs dp;
-                    if ((rc = upload_plan(ctx, plan, dp))) return rc;
-                    HIPCHK(ctx, launch_init(dp.frames, 1, plan.max_M, (HypState *)ctx->hs.p, (PoseEval *)ctx->pose.p,
-                                            (int *)ctx->hlev.p, MODE_DIAG, frame->poses_in, l, ctx->stream));
-                    const LaunchGroup &g = plan.groups[0];
-                    PassArgs a;
-                    a.frames = dp.frames;
-                    a.items = dp.items + g.item_off;
-                    a.n_items = g.n_items;
-                    a.level = l;
-                    a.pose = (const PoseEval *)ctx->pose.p;
-                    a.hlev = (const int *)ctx->hlev.p;
-                    a.partials = (float *)ctx->partials.p;
-                    HIPCHK(ctx, launch_pass(L.C, L.dtype, g.tc, a, ctx->stream));   // warm-up
-                    hipEvent_t e0 = pool_event(ctx), e1 = pool_event(ctx);
-                    HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
-                    const int reps = 3;
-                    for (int r = 0; r < reps; ++r) HIPCHK(ctx, launch_pass(L.C, L.dtype, g.tc, a, ctx->stream));
-                    HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
-                    HIPCHK(ctx, hipEventSynchronize(e1));
-                    float ms = 0;
-                    HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
-                    ctx->event_pool.push_back(e0);
-                    ctx->event_pool.push_back(e1);
-                    if (ms < best_ms) {
-                        best_ms = ms;
-                        best = tc;
-                    }
-                }
-            }
+        keys[l] = tune_key(L.C, L.dtype, L.N, frame->M);
+        if (!ctx->tuned.count(keys[l]) && std::find(todo.begin(), todo.end(), keys[l]) == todo.end())
+            todo.push_back(keys[l]);
+    }
+    if (todo.empty()) return PILOT_OK;
+    if ((rc = collect_timings(ctx))) return rc;           // earlier profiled launches go to the counters
+
+    std::vector<TileConfig> cand;
+    for (int variant : {1, 2})
+        for (int G : {4, 8, 16})
+            for (int ppg : {2, 4, 8, 16})
+                for (int bpc : {0, 2, 4}) cand.push_back(TileConfig{G, ppg, bpc, variant});
+
+    // scratch outputs of the timed solves
+    const int M = frame->M;
+    void *buf = nullptr;
+    const size_t bytes = (size_t)M * (12 + 1) * sizeof(double) + (size_t)M * 2 * sizeof(int32_t) + 64;
+    HIPCHK(ctx, hipMalloc(&buf, bytes));
+    pilot_result res;
+    res.poses_out = (double *)buf;
+    res.cost = res.poses_out + (size_t)M * 12;
+    res.iterations = (int32_t *)(res.cost + M);
+    res.status = res.iterations + M;
+    res.best = res.status + M;
+    unsigned long long pairs_saved[kStatClasses] = {0};
+    bool have_pairs = false;
+
+    auto apply = [&](const TileConfig &tc) {
+        for (const std::string &k : todo) ctx->tuned[k] = tc;
+    };
+    // score[c][k]: lowest summed pass ms of candidate c on key k
+    std::vector<std::vector<double>> score(cand.size(), std::vector<double>(todo.size(), 1e300));
+    auto run = [&](size_t c) -> int {
+        apply(cand[c]);
+        double ms[PILOT_MAX_LEVELS];
+        int r = timed_solve(ctx, frame, &res, ms);
+        if (r) return r;
+        std::vector<double> per(todo.size(), 0.0);
+        for (int l = 0; l < frame->n_levels; ++l) {
+            const auto it = std::find(todo.begin(), todo.end(), keys[l]);
+            if (it != todo.end()) per[it - todo.begin()] += ms[l];
         }
-        ctx->tuned[key] = best;
+        for (size_t k = 0; k < todo.size(); ++k) score[c][k] = std::min(score[c][k], per[k]);
+        return PILOT_OK;
+    };
+
+    rc = PILOT_OK;
+    do {
+        if (ctx->pairs.p) {
+            if (hipMemcpy(pairs_saved, ctx->pairs.p, sizeof pairs_saved, hipMemcpyDeviceToHost) != hipSuccess) {
+                rc = fail(ctx, PILOT_EDEVICE, "hipMemcpy of counters failed");
+                break;
+            }
+            have_pairs = true;
+        }
+        // bring the clocks up (an idle GPU runs the first tens of ms slower)
+        apply(heuristic_tile(ctx, frame->level[0].C, frame->level[0].dtype, frame->level[0].N, M));
+        double warm = 0.0;
+        for (int k = 0; k < 50 && warm < 40.0 && rc == PILOT_OK; ++k) {
+            double ms[PILOT_MAX_LEVELS];
+            rc = timed_solve(ctx, frame, &res, ms);
+            for (int l = 0; l < frame->n_levels; ++l) warm += ms[l];
+        }
+        if (rc) break;
+        for (size_t c = 0; c < cand.size() && rc == PILOT_OK; ++c) rc = run(c);
+        if (rc) break;
+        // second round for the 8 best of each key
+        std::vector<char> again(cand.size(), 0);
+        for (size_t k = 0; k < todo.size(); ++k) {
+            std::vector<size_t> order(cand.size());
+            for (size_t c = 0; c < cand.size(); ++c) order[c] = c;
+            std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return score[a][k] < score[b][k]; });
+            for (size_t i = 0; i < 8 && i < order.size(); ++i) again[order[i]] = 1;
+        }
+        for (size_t c = 0; c < cand.size() && rc == PILOT_OK; ++c)
+            if (again[c]) rc = run(c);
+    } while (false);
+    if (have_pairs && ctx->pairs.p) {
+        if (hipMemcpy(ctx->pairs.p, pairs_saved, sizeof pairs_saved, hipMemcpyHostToDevice) != hipSuccess && !rc)
+            rc = fail(ctx, PILOT_EDEVICE, "hipMemcpy of counters failed");
+    }
+    hipFree(buf);
+    for (const std::string &k : todo) ctx->tuned.erase(k);
+    if (rc) return rc;
+
+    for (size_t k = 0; k < todo.size(); ++k) {
+        size_t bi = 0;
+        for (size_t c = 1; c < cand.size(); ++c)
+            if (score[c][k] < score[bi][k]) bi = c;
+        ctx->tuned[todo[k]] = cand[bi];
         if (!ctx->tune_cache.empty()) {
             std::ofstream out(ctx->tune_cache, std::ios::app);
-            out << key << " " << best.G << " " << best.PPG << " " << best.grid << " " << best.variant << "\n";
+            out << todo[k] << " " << cand[bi].G << " " << cand[bi].PPG << " " << cand[bi].grid << " "
+                << cand[bi].variant << "\n";
         }
     }
     return PILOT_OK;

@@ -217,6 +217,11 @@ GRAVITY_LOSS = (LOSS_HUBER, (3.0 * math.radians(GRAVITY_NOISE_DEG)) ** 2)
 RANGE_LOSS = (LOSS_HUBER, (3.0 * RANGE_NOISE_M) ** 2)
 LAMBDA_IMU = FEATURE_NOISE ** 2 / math.radians(GRAVITY_NOISE_DEG) ** 2
 LAMBDA_RANGE = FEATURE_NOISE ** 2 / RANGE_NOISE_M ** 2
+# adaptive prior scales: a prior's gradient is capped at ALPHA_RATIO times
+# the visual gradient, and residuals beyond 5 sigma are gated down
+ALPHA_RATIO = 1.0
+GRAVITY_GATE = 5.0 * math.radians(GRAVITY_NOISE_DEG)
+RANGE_GATE = 5.0 * RANGE_NOISE_M
 
 LM_DEFAULTS = dict(tau=1e-6, up=10.0, down=10.0, lambda_min_rel=1e-12,
                    lambda_max_rel=1e8, step_tol_t=1e-5, step_tol_r=1e-7,
@@ -264,6 +269,10 @@ class Frame:
     meta: dict = field(default_factory=dict)
     keep_top: int = 0                   # top-K pruning after prune_level (0 = none)
     prune_level: int = 0
+    adaptive_priors: int = 0            # adaptive prior scales with residual gates
+    alpha_ratio: float = ALPHA_RATIO
+    gravity_gate: float = GRAVITY_GATE
+    range_gate: float = RANGE_GATE
 
     @property
     def M(self) -> int:

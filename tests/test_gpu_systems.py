@@ -286,3 +286,33 @@ def test_device_lift_matches_oracle(dtype):
         gi = gr.view(torch.int16).numpy().astype(np.int32)
         ei = expect.view(torch.int16).numpy().astype(np.int32)
         assert np.abs(gi - ei).max() <= 1                 # one bf16 ulp (double rounding f64 -> f32 -> bf16)
+
+
+def test_autotune_writes_every_level_key_and_stays_correct(tmp_path):
+    """The tuner times solves of the caller's frame, records one tile per
+    level shape in the cache file, and a later context reads them back; the
+    tuned solve still matches the oracle."""
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    f = small(41, N=600, M=9)
+    d = DeviceFrame(f)
+    cache = tmp_path / "tiles.txt"
+    say("autotune small frame")
+    ctx = Context(0, tune_cache=str(cache))
+    st0 = ctx.stats(reset=False)
+    ctx.autotune(d)
+    torch.cuda.synchronize()
+    st1 = ctx.stats(reset=False)
+    assert sum(st1.pairs) == sum(st0.pairs) and sum(st1.launches) == sum(st0.launches)   # counters untouched
+    lines = [ln.split() for ln in cache.read_text().splitlines()]
+    keys = {f"C{L.C}_d0_N{int(math.floor(math.log2(L.N)))}_M{int(math.floor(math.log2(f.M)))}_v2" for L in f.levels}
+    assert {ln[0] for ln in lines} == keys and len(lines) == len(keys)
+    for ln in lines:
+        G, ppg, bpc, var = map(int, ln[1:])
+        assert G in (4, 8, 16) and ppg in (2, 4, 8, 16) and bpc in (0, 2, 4) and var in (1, 2)
+    ctx2 = Context(0, tune_cache=str(cache))
+    for L in f.levels:
+        assert "tuned=1" in ctx2.tile_choice(L.C, 0, L.N, f.M)
+    out = ctx2.solve([d])[0].numpy()
+    torch.cuda.synchronize()
+    rows, fails = compare_solutions(f, out, oracle.solve(f, threads=8), POSE_TOL_M, POSE_TOL_DEG, "tuned")
+    assert not fails, fails

@@ -34,7 +34,11 @@ MUTANTS = {
                                "if (st[j].c > st[i].c || (st[j].c == st[i].c && j < i)) better++;"),
     "selection_tie": ("if (best < 0 || cost[m] < cost[best]) best = m;",
                       "if (best < 0 || cost[m] <= cost[best]) best = m;"),
-    "gravity_prior_weight": ("c += f->lambda_imu * rho;", "c += rho;"),
+    "gravity_prior_weight": ("c += a_grav * rho;", "c += rho;"),
+    "gate_not_squared": ("alpha[s] *= (gate[s] / rn) * (gate[s] / rn);", "alpha[s] *= (gate[s] / rn);"),
+    "ratio_cap_direction": ("lam[s] * gn > f->alpha_ratio * gv", "lam[s] * gn < f->alpha_ratio * gv"),
+    "scales_from_candidate_gradient": ("orc_prior_scales(f, st->T, g, st->alpha);",
+                                       "orc_prior_scales(f, st->T, H, st->alpha);"),
 }
 
 

@@ -426,3 +426,118 @@ def test_paper_hypothesis_grid():
     xs = sorted(set(round(a, 9) for a, _, _ in offs))
     assert xs[0] == -g["xy_range_m"] and xs[-1] == g["xy_range_m"] and len(xs) == 11
     assert sum(gold["schedule"]["iters_coarse_to_fine"]) == gold["schedule"]["unrolled_steps"]
+
+
+# ---------------------------------------------------------------- adaptive prior scales
+def _prior_parts(f, level, T):
+    """Visual gradient, unit-scale gravity and range gradients and residual
+    norms, taken from the fixed-scale objective with the priors switched on
+    one at a time."""
+    import copy
+    base = copy.copy(f)
+    base.use_gravity = base.use_range = 0
+    gv = oracle.linearize(oracle.OracleFrame(base), level, T)[1]
+    fg = copy.copy(f)
+    fg.use_range, fg.lambda_imu = 0, 1.0
+    g1 = oracle.linearize(oracle.OracleFrame(fg), level, T)[1]
+    fr = copy.copy(f)
+    fr.use_gravity, fr.lambda_range = 0, 1.0
+    g2 = oracle.linearize(oracle.OracleFrame(fr), level, T)[1]
+    of = oracle.OracleFrame(f)
+    return gv, g1 - gv, g2 - gv, np.linalg.norm(oracle.gravity(of, T)[0]), abs(oracle.range_term(of, T)[0])
+
+
+def _off_pose(f):
+    # 4 m and 1.5 deg of roll off the truth: both prior residuals are large
+    return left_perturb(f.gt_pose, np.array([2.0, -3.0, 1.5, math.radians(1.5), 0.0, 0.0]))
+
+
+def test_adaptive_scales_reduce_to_fixed_without_cap_or_gate():
+    f = small_frame(M=4)
+    fixed = oracle.solve(f, threads=2)
+    assert np.array_equal(fixed["alpha"], np.tile([f.lambda_imu, f.lambda_range], (4, 1)))
+    f.adaptive_priors, f.alpha_ratio, f.gravity_gate, f.range_gate = 1, 0.0, 0.0, 0.0
+    T = _off_pose(f)
+    a = oracle.prior_scales(oracle.OracleFrame(f), T, np.ones(6))
+    assert a[0] == f.lambda_imu and a[1] == f.lambda_range
+    ad = oracle.solve(f, threads=2)
+    for k in ("poses", "cost", "iterations", "status", "alpha"):
+        assert np.array_equal(ad[k], fixed[k]), k
+    f.use_gravity = 0
+    assert oracle.prior_scales(oracle.OracleFrame(f), T, np.ones(6))[0] == 0.0
+
+
+def test_ratio_cap_balances_prior_and_visual_gradients():
+    f = small_frame()
+    T = _off_pose(f)
+    gv, gg, gr, _, _ = _prior_parts(f, 1, T)
+    nv, ng, nr = np.linalg.norm(gv), np.linalg.norm(gg), np.linalg.norm(gr)
+    f.adaptive_priors, f.gravity_gate, f.range_gate = 1, 0.0, 0.0
+    for beta in (1e-4, 1e-2, 1.0, 1e6):
+        f.alpha_ratio = beta
+        a = oracle.prior_scales(oracle.OracleFrame(f), T, gv)
+        for s, lam, n in ((0, f.lambda_imu, ng), (1, f.lambda_range, nr)):
+            if lam * n > beta * nv:            # capped: the scaled prior gradient equals beta |g_vis|
+                assert a[s] < lam
+                assert a[s] * n == pytest.approx(beta * nv, rel=1e-8)
+            else:
+                assert a[s] == lam
+    f.alpha_ratio = 1e-4
+    a = oracle.prior_scales(oracle.OracleFrame(f), T, gv)
+    assert a[0] < f.lambda_imu and a[1] < f.lambda_range           # the small ratio binds both
+
+
+def test_residual_gate_scales_by_inverse_square():
+    f = small_frame()
+    T = _off_pose(f)
+    gv, _, _, rg, rr = _prior_parts(f, 1, T)
+    assert rg > 1e-3 and rr > 0.1
+    f.adaptive_priors, f.alpha_ratio = 1, 0.0
+    for k in (0.25, 0.5, 1.0, 2.0):
+        f.gravity_gate, f.range_gate = k * rg, k * rr
+        a = oracle.prior_scales(oracle.OracleFrame(f), T, gv)
+        expect = min(1.0, k * k)
+        assert a[0] == pytest.approx(f.lambda_imu * expect, rel=1e-12)
+        assert a[1] == pytest.approx(f.lambda_range * expect, rel=1e-12)
+
+
+def test_solve_reports_the_scales_of_the_level_start():
+    f = small_frame(M=3, levels=((120, 160, 32),), iters=(0,))
+    f.adaptive_priors, f.alpha_ratio = 1, 0.05
+    r = oracle.solve(f, threads=2)
+    of = oracle.OracleFrame(f)
+    for m in range(3):
+        gv = oracle.linearize_visual(of, 0, f.poses[m])[1]
+        assert np.array_equal(r["alpha"][m], oracle.prior_scales(of, f.poses[m], gv))
+
+
+def test_adaptive_accepted_costs_never_increase_within_a_level():
+    f = S.make_frame(2, 3, N=400, M=6, level_shapes=((60, 80, 16), (120, 160, 32)), iters=(25, 25))
+    f.lm["step_tol_t"] = f.lm["step_tol_r"] = 0.0
+    f.adaptive_priors, f.alpha_ratio = 1, 0.05
+    r = oracle.solve(f, threads=4, trace=True)
+    tr = r["trace"]
+    for m in range(tr.shape[0]):
+        rows = tr[m][~np.isnan(tr[m][:, 0])]
+        for lvl in np.unique(rows[:, 0]):
+            R = rows[rows[:, 0] == lvl]
+            assert np.all(np.diff(R[:, 1]) <= 0)
+
+
+def test_gate_protects_against_a_corrupted_range_reading():
+    """A range reading 40 m too long pulls a fixed-scale solve off the truth;
+    with the residual gate the solution stays with the visual one."""
+    f = S.make_frame(1, 0, noise=False)
+    f.lambda_range = 1.0
+    f.d_range += 40.0
+    fixed = oracle.solve(f, threads=2)
+    f.adaptive_priors = 1
+    gated = oracle.solve(f, threads=2)
+    f.use_range = 0
+    visual = oracle.solve(f, threads=2)
+    e_fixed = S.pose_errors(fixed["poses"][0], f.gt_pose)[0][0]
+    e_gated = S.pose_errors(gated["poses"][0], f.gt_pose)[0][0]
+    e_vis = S.pose_errors(visual["poses"][0], f.gt_pose)[0][0]
+    assert e_vis < 1e-5
+    assert e_fixed > 10.0, e_fixed                      # the bad reading wins at a fixed scale
+    assert e_gated < 0.5 and e_gated < e_fixed / 50.0, (e_gated, e_fixed)
