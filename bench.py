@@ -378,6 +378,7 @@ def run_serving_config(args, worlds):
             s.lambda_min_rel, s.lambda_max_rel = lm["lambda_min_rel"], lm["lambda_max_rel"]
             s.step_tol_t, s.step_tol_r, s.z_min = lm["step_tol_t"], lm["step_tol_r"], lm["z_min"]
             s.min_valid = lm["min_valid"]
+            s.cost_tol = lm["cost_tol"]
             offs = torch.as_tensor(spec.offsets, device=dev)
             keep.append(offs)
             s.M = int(spec.offsets.shape[0])

@@ -134,7 +134,7 @@ typedef struct {
     double tau, lambda_up, lambda_down, lambda_min_rel, lambda_max_rel;
     double step_tol_t, step_tol_r, z_min;
     int32_t min_valid;          /* fewer visible anchors at a level start: DEGENERATE */
-    int32_t reserved;
+    int32_t adaptive_priors;    /* 0: fixed scales lambda_imu, lambda_range; else see below */
     /* Optional hypothesis generation on the device (supplement "Multi-Hypothesis
      * Refinement": hypotheses around the propagated prior in (x, y, yaw)).
      * When hyp_offsets is non-NULL, poses_in is ignored and hypothesis m is the
@@ -154,6 +154,25 @@ typedef struct {
      * Requires 0 <= prune_level < n_levels - 1 and M <= 8192. */
     int32_t keep_top;
     int32_t prune_level;
+    /* Adaptive prior scales (supplement, Sensor-Prior Fusion in LM: the scales
+     * of the gravity and range terms follow the relative gradient magnitudes
+     * and residual-dependent gates).  With adaptive_priors != 0 each
+     * hypothesis sets, at the start of every level (its pose there), for each
+     * enabled prior s with base scale lambda_s, unit-scale gradient
+     * g_s = J_s^T rho_s' r_s and residual norm |r_s|:
+     *   alpha_s = lambda_s * min(1, alpha_ratio |g_vis| / (lambda_s |g_s|))
+     *                      * min(1, (gate_s / |r_s|)^2)
+     * (g_vis: gradient of the visual term; a factor is 1 when its parameter is
+     * <= 0) and keeps it for the rest of the level, so the level's objective
+     * is fixed.  All three must be finite and >= 0. */
+    double alpha_ratio;
+    double gravity_gate;        /* on |R g_world - g_imu|                           */
+    double range_gate;          /* metres, on the range residual                      */
+    /* Function tolerance of the LM control: a candidate whose total cost
+     * differs from the current one by at most cost_tol * cost ends the level
+     * as CONVERGED (the candidate is accepted if its cost is lower).  0 turns
+     * the rule off; finite and >= 0. */
+    double cost_tol;
 } pilot_frame;
 
 /* Caller-owned device buffers. */
@@ -163,6 +182,8 @@ typedef struct {
     int32_t *iterations;        /* M iterations executed, all levels                  */
     int32_t *status;            /* M PILOT_CONVERGED .. PILOT_PRUNED                  */
     int32_t *best;              /* 1 index (or -1)                                    */
+    double *alpha;              /* M*2 or NULL: gravity and range scales each
+                                   hypothesis used at the last level it started  */
 } pilot_result;
 
 typedef struct {

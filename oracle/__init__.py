@@ -49,7 +49,7 @@ class _Frame(C.Structure):
                 ("tol_t", C.c_double), ("tol_r", C.c_double), ("z_min", C.c_double),
                 ("min_valid", C.c_int), ("keep_top", C.c_int), ("prune_level", C.c_int),
                 ("adaptive", C.c_int), ("alpha_ratio", C.c_double), ("grav_gate", C.c_double),
-                ("range_gate", C.c_double)]
+                ("range_gate", C.c_double), ("cost_tol", C.c_double)]
 
 
 def build(force: bool = True) -> str:
@@ -160,6 +160,7 @@ class OracleFrame:
         s.lam_min_rel, s.lam_max_rel = lm["lambda_min_rel"], lm["lambda_max_rel"]
         s.tol_t, s.tol_r, s.z_min = lm["step_tol_t"], lm["step_tol_r"], lm["z_min"]
         s.min_valid = int(lm["min_valid"])
+        s.cost_tol = float(lm.get("cost_tol", 0.0))
         s.keep_top = int(getattr(frame, "keep_top", 0))
         s.prune_level = int(getattr(frame, "prune_level", 0))
         s.adaptive = int(getattr(frame, "adaptive_priors", 0))

@@ -599,6 +599,8 @@ static void run_level(const orc_frame *f, int l, hyp_state *st, double *trace, i
         orc_compose(E, st->T, Tc);
         linearize_at(f, l, Tc, st->alpha, Hc, gc, &cc, &nc);
         if (tr) { tr[0] = l; tr[1] = c; tr[2] = cc; tr[3] = 0; }
+        /* the cost is flat to within cost_tol: nothing left to gain */
+        const int flat = f->cost_tol > 0.0 && fabs(cc - c) <= f->cost_tol * c;
         if (cc < c) {
             if (tr) tr[3] = 1;
             memcpy(st->T, Tc, sizeof(Tc));
@@ -610,7 +612,10 @@ static void run_level(const orc_frame *f, int l, hyp_state *st, double *trace, i
             if (lam < lam_min) lam = lam_min;
             double nt = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
             double nr = sqrt(dx[3] * dx[3] + dx[4] * dx[4] + dx[5] * dx[5]);
-            if (nt < f->tol_t && nr < f->tol_r) { lvl_status = ORC_CONVERGED; break; }
+            if ((nt < f->tol_t && nr < f->tol_r) || flat) { lvl_status = ORC_CONVERGED; break; }
+        } else if (flat) {
+            lvl_status = ORC_CONVERGED;
+            break;
         } else {
             lam *= f->up;
             if (lam >= lam_max) { lvl_status = ORC_STALLED; break; }

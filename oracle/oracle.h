@@ -67,6 +67,10 @@ typedef struct {
      * that level; see orc_prior_scales */
     int adaptive;
     double alpha_ratio, grav_gate, range_gate;
+    /* function tolerance: a candidate whose cost differs from the current
+     * one by at most cost_tol * cost ends the level as CONVERGED (accepted
+     * if lower); 0 switches the rule off */
+    double cost_tol;
 } orc_frame;
 
 /* SE(3) */

@@ -49,13 +49,16 @@ class Frame(C.Structure):
                 ("tau", C.c_double), ("lambda_up", C.c_double), ("lambda_down", C.c_double),
                 ("lambda_min_rel", C.c_double), ("lambda_max_rel", C.c_double),
                 ("step_tol_t", C.c_double), ("step_tol_r", C.c_double), ("z_min", C.c_double),
-                ("min_valid", C.c_int32), ("reserved", C.c_int32),
+                ("min_valid", C.c_int32), ("adaptive_priors", C.c_int32),
                 ("prior_poses", _dp), ("prior_best", _vp), ("hyp_offsets", _dp),
-                ("keep_top", C.c_int32), ("prune_level", C.c_int32)]
+                ("keep_top", C.c_int32), ("prune_level", C.c_int32),
+                ("alpha_ratio", C.c_double), ("gravity_gate", C.c_double), ("range_gate", C.c_double),
+                ("cost_tol", C.c_double)]
 
 
 class Result(C.Structure):
-    _fields_ = [("poses_out", _dp), ("cost", _dp), ("iterations", _vp), ("status", _vp), ("best", _vp)]
+    _fields_ = [("poses_out", _dp), ("cost", _dp), ("iterations", _vp), ("status", _vp), ("best", _vp),
+                ("alpha", _dp)]
 
 
 class Stats(C.Structure):

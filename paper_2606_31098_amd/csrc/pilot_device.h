@@ -47,13 +47,14 @@ struct FrameDev {
     // LM control
     double tau, up, down, lmin_rel, lmax_rel, tol_t, tol_r;
     double z_min;
-    int min_valid, pad2;
+    int min_valid, adaptive;
+    double alpha_ratio, grav_gate, range_gate, cost_tol;
     const double *poses_in;
     const double *prior_poses;   // device hypothesis generation (hyp_offsets non-NULL)
     const int *prior_best;
     const double *hyp_offsets;
     // outputs
-    double *poses_out, *cost_out;
+    double *poses_out, *cost_out, *alpha_out;
     int *iters_out, *status_out, *best_out;
     // diagnostic outputs (pilot_linearize)
     double *diag_H, *diag_g, *diag_cost;
@@ -86,6 +87,7 @@ struct HypState {
     double H[21];    // system at T (upper triangle, row by row)
     double g[6];
     double cost, lam, lmin, lmax;
+    double alpha[2]; // prior scales (gravity, range) of the current level
     int level, phase, it_level, it_total, status, nvalid, pad0, pad1;
 };
 

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpilogueArgs e)
         for (int i = 0; i < 21; ++i) Hd[i] = S[i];
         for (int i = 0; i < 6; ++i) gd[i] = S[21 + i];
         double cost = S[kCostSlot];
-        add_priors(*f, e.hs[gh].T, Hd, gd, cost);
+        add_priors(*f, e.hs[gh].T, f->use_g ? f->lam_imu : 0.0, f->use_r ? f->lam_range : 0.0, Hd, gd, cost);
         for (int i = 0; i < 21; ++i) f->diag_H[(size_t)m * 21 + i] = Hd[i];
         for (int i = 0; i < 6; ++i) f->diag_g[(size_t)m * 6 + i] = gd[i];
         f->diag_cost[m] = cost;
@@ -173,6 +173,8 @@ __global__ __launch_bounds__(256) void init_kernel(const FrameDev *frames, HypSt
     for (int i = 0; i < 21; ++i) s.H[i] = 0.0;
     s.cost = __longlong_as_double(0x7ff8000000000000LL);   // NaN until evaluated
     s.lam = s.lmin = s.lmax = 0.0;
+    s.alpha[0] = f.use_g ? f.lam_imu : 0.0;
+    s.alpha[1] = f.use_r ? f.lam_range : 0.0;
     s.level = (mode == MODE_DIAG) ? dlevel : 0;
     s.phase = PHASE_START;
     s.it_level = s.it_total = 0;
@@ -224,6 +226,10 @@ __global__ __launch_bounds__(256) void finalize_kernel(const FrameDev *frames, c
         f.cost_out[m] = s.cost;
         f.iters_out[m] = s.it_total;
         f.status_out[m] = s.status;
+        if (f.alpha_out) {
+            f.alpha_out[2 * m] = s.alpha[0];
+            f.alpha_out[2 * m + 1] = s.alpha[1];
+        }
         if (s.status != ST_DEGENERATE && s.status != ST_PRUNED && isfinite(s.cost) && (bi < 0 || s.cost < bc)) {
             bc = s.cost;
             bi = m;

@@ -136,21 +136,53 @@ __device__ inline void dsm_lookup(const FrameDev &f, double x, double y, double 
     hy = ci ? 0.0 : (bot - top) / f.dsm_gsd;
 }
 
-// Add the gravity (Eq. (3)) and laser-range (Eqs. (4)-(6)) terms at pose T.
-__device__ inline void add_priors(const FrameDev &f, const double T[12], double H[21], double g[6], double &cost)
+// Gravity residual of Eq. (3) at pose T: gc = R g_world, r = gc - g_imu.
+// Under T <- Exp(xi) T the Jacobian is [0 | -[gc]x].
+__device__ inline void gravity_residual(const FrameDev &f, const double T[12], double gc[3], double r[3])
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        gc[i] = T[3 * i] * f.g_world[0] + T[3 * i + 1] * f.g_world[1] + T[3 * i + 2] * f.g_world[2];
+        r[i] = gc[i] - f.g_imu[i];
+    }
+}
+
+// Range residual of Eqs. (4)-(6) at pose T and its Jacobian row J.
+__device__ inline double range_residual(const FrameDev &f, const double T[12], double J[6])
+{
+    const double qt[3] = {f.q[0] - T[9], f.q[1] - T[10], f.q[2] - T[11]};
+    double P[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) P[i] = T[i] * qt[0] + T[3 + i] * qt[1] + T[6 + i] * qt[2];   // R^T qt
+    double h, hx, hy;
+    dsm_lookup(f, P[0], P[1], h, hx, hy);
+    // dr/dP = a = (-hx, -hy, 1); J = [-R a, (R a) x q]
+    double Ra[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Ra[i] = -T[3 * i] * hx - T[3 * i + 1] * hy + T[3 * i + 2];
+    J[0] = -Ra[0];
+    J[1] = -Ra[1];
+    J[2] = -Ra[2];
+    J[3] = Ra[1] * f.q[2] - Ra[2] * f.q[1];
+    J[4] = Ra[2] * f.q[0] - Ra[0] * f.q[2];
+    J[5] = Ra[0] * f.q[1] - Ra[1] * f.q[0];
+    return P[2] - h;
+}
+
+// Add the gravity (Eq. (3)) and laser-range (Eqs. (4)-(6)) terms at pose T
+// with scales ag, ar (the lambda of Eq. (7), the alpha of the supplement's
+// H_total, g_total).
+__device__ inline void add_priors(const FrameDev &f, const double T[12], double ag, double ar, double H[21],
+                                  double g[6], double &cost)
 {
     if (f.use_g) {
         double gc[3], r[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            gc[i] = T[3 * i] * f.g_world[0] + T[3 * i + 1] * f.g_world[1] + T[3 * i + 2] * f.g_world[2];
-            r[i] = gc[i] - f.g_imu[i];
-        }
+        gravity_residual(f, T, gc, r);
         double rho, drho;
         robust_f64(f.grav_kind, f.grav_b, r[0] * r[0] + r[1] * r[1] + r[2] * r[2], rho, drho);
-        cost += f.lam_imu * rho;
-        const double W = f.lam_imu * drho;
-        // J = [0 | -[gc]x]:  J^T J = |gc|^2 I - gc gc^T,  J^T r = gc x r  (rotation block)
+        cost += ag * rho;
+        const double W = ag * drho;
+        // J^T J = |gc|^2 I - gc gc^T,  J^T r = gc x r  (rotation block)
         const double n2 = gc[0] * gc[0] + gc[1] * gc[1] + gc[2] * gc[2];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -161,31 +193,60 @@ __device__ inline void add_priors(const FrameDev &f, const double T[12], double 
         g[5] += W * (gc[0] * r[1] - gc[1] * r[0]);
     }
     if (f.use_r) {
-        const double qt[3] = {f.q[0] - T[9], f.q[1] - T[10], f.q[2] - T[11]};
-        double P[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) P[i] = T[i] * qt[0] + T[3 + i] * qt[1] + T[6 + i] * qt[2];   // R^T qt
-        double h, hx, hy;
-        dsm_lookup(f, P[0], P[1], h, hx, hy);
-        const double r = P[2] - h;
+        double J[6];
+        const double r = range_residual(f, T, J);
         double rho, drho;
         robust_f64(f.range_kind, f.range_b, r * r, rho, drho);
-        cost += f.lam_range * rho;
-        const double W = f.lam_range * drho;
-        // dr/dP = a = (-hx, -hy, 1); J = [-R a, (R a) x q]
-        double Ra[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) Ra[i] = -T[3 * i] * hx - T[3 * i + 1] * hy + T[3 * i + 2];
-        const double J[6] = {-Ra[0], -Ra[1], -Ra[2],
-                             Ra[1] * f.q[2] - Ra[2] * f.q[1],
-                             Ra[2] * f.q[0] - Ra[0] * f.q[2],
-                             Ra[0] * f.q[1] - Ra[1] * f.q[0]};
+        cost += ar * rho;
+        const double W = ar * drho;
 #pragma unroll
         for (int a = 0; a < 6; ++a) {
 #pragma unroll
             for (int b = a; b < 6; ++b) H[tri(a, b)] += W * J[a] * J[b];
             g[a] += W * J[a] * r;
         }
+    }
+}
+
+// Prior scales at pose T given the visual gradient gv (supplement,
+// Sensor-Prior Fusion in LM): each enabled prior's base scale is reduced so
+// that its gradient does not exceed alpha_ratio times the visual one, and by
+// (gate / |r|)^2 when its residual exceeds the gate.  Fixed scales unless
+// f.adaptive; 0 for a disabled prior.
+__device__ inline void prior_scales(const FrameDev &f, const double T[12], const double gv[6], double alpha[2])
+{
+    alpha[0] = f.use_g ? f.lam_imu : 0.0;
+    alpha[1] = f.use_r ? f.lam_range : 0.0;
+    if (!f.adaptive) return;
+    double nv = 0.0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) nv += gv[a] * gv[a];
+    nv = sqrt(nv);
+    if (f.use_g) {
+        double gc[3], r[3], rho, drho;
+        gravity_residual(f, T, gc, r);
+        const double s = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        robust_f64(f.grav_kind, f.grav_b, s, rho, drho);
+        // unit-scale gradient drho * J^T r = drho * (0, gc x r)
+        const double c0 = gc[1] * r[2] - gc[2] * r[1], c1 = gc[2] * r[0] - gc[0] * r[2],
+                     c2 = gc[0] * r[1] - gc[1] * r[0];
+        const double gn = fabs(drho) * sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+        const double rn = sqrt(s);
+        if (f.alpha_ratio > 0.0 && f.lam_imu * gn > f.alpha_ratio * nv) alpha[0] *= f.alpha_ratio * nv / (f.lam_imu * gn);
+        if (f.grav_gate > 0.0 && rn > f.grav_gate) alpha[0] *= (f.grav_gate / rn) * (f.grav_gate / rn);
+    }
+    if (f.use_r) {
+        double J[6], rho, drho;
+        const double r = range_residual(f, T, J);
+        robust_f64(f.range_kind, f.range_b, r * r, rho, drho);
+        double n2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) n2 += J[a] * J[a];
+        const double gn = fabs(drho * r) * sqrt(n2);
+        const double rn = fabs(r);
+        if (f.alpha_ratio > 0.0 && f.lam_range * gn > f.alpha_ratio * nv)
+            alpha[1] *= f.alpha_ratio * nv / (f.lam_range * gn);
+        if (f.range_gate > 0.0 && rn > f.range_gate) alpha[1] *= (f.range_gate / rn) * (f.range_gate / rn);
     }
 }
 
@@ -257,7 +318,10 @@ __device__ inline void lm_advance(const FrameDev &f, HypState &s, const double *
     double cost = S[kCostSlot];
     const int n = (int)S[27];
     const double *Tp = (s.phase == PHASE_START) ? s.T : s.Tc;
-    add_priors(f, Tp, H, g, cost);
+    // the prior scales are set at the level's starting pose and held for the
+    // level, so its objective is fixed and a cost decrease is well defined
+    if (s.phase == PHASE_START) prior_scales(f, Tp, g, s.alpha);
+    add_priors(f, Tp, s.alpha[0], s.alpha[1], H, g, cost);
 
     bool finite = isfinite(cost);
 #pragma unroll
@@ -287,7 +351,8 @@ __device__ inline void lm_advance(const FrameDev &f, HypState &s, const double *
         propose(f, s, p32, hlev);
         return;
     }
-    // candidate evaluation
+    // candidate evaluation; a cost flat to within cost_tol ends the level
+    const bool flat = finite && f.cost_tol > 0.0 && fabs(cost - s.cost) <= f.cost_tol * s.cost;
     if (finite && cost < s.cost) {
 #pragma unroll
         for (int i = 0; i < 12; ++i) s.T[i] = s.Tc[i];
@@ -300,10 +365,13 @@ __device__ inline void lm_advance(const FrameDev &f, HypState &s, const double *
         s.lam = fmax(s.lam / f.down, s.lmin);
         const double nt = sqrt(s.dxi[0] * s.dxi[0] + s.dxi[1] * s.dxi[1] + s.dxi[2] * s.dxi[2]);
         const double nr = sqrt(s.dxi[3] * s.dxi[3] + s.dxi[4] * s.dxi[4] + s.dxi[5] * s.dxi[5]);
-        if (nt < f.tol_t && nr < f.tol_r) {
+        if ((nt < f.tol_t && nr < f.tol_r) || flat) {
             level_done(f, s, ST_CONVERGED, p32, hlev);
             return;
         }
+    } else if (flat) {
+        level_done(f, s, ST_CONVERGED, p32, hlev);
+        return;
     } else {
         s.lam *= f.up;
         if (s.lam >= s.lmax) {

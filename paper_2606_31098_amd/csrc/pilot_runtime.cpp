@@ -246,6 +246,15 @@ int validate_frame(pilot_ctx *ctx, const pilot_frame *f, int fi, bool need_poses
     if (!(f->z_min >= 0) || !std::isfinite(f->z_min)) return fail(ctx, PILOT_EINVAL, "frames[%d].z_min: must be finite and >= 0", fi);
     if (f->min_valid < 0) return fail(ctx, PILOT_EINVAL, "frames[%d].min_valid: must be >= 0", fi);
     if (f->keep_top < 0) return fail(ctx, PILOT_EINVAL, "frames[%d].keep_top: must be >= 0", fi);
+    if (!std::isfinite(f->cost_tol) || f->cost_tol < 0.0)
+        return fail(ctx, PILOT_EINVAL, "frames[%d].cost_tol: must be finite and >= 0", fi);
+    if (f->adaptive_priors) {
+        const double v[3] = {f->alpha_ratio, f->gravity_gate, f->range_gate};
+        const char *nm[3] = {"alpha_ratio", "gravity_gate", "range_gate"};
+        for (int i = 0; i < 3; ++i)
+            if (!std::isfinite(v[i]) || v[i] < 0.0)
+                return fail(ctx, PILOT_EINVAL, "frames[%d].%s: must be finite and >= 0", fi, nm[i]);
+    }
     if (f->keep_top > 0) {
         if (f->prune_level < 0 || f->prune_level >= f->n_levels - 1)
             return fail(ctx, PILOT_EINVAL, "frames[%d].prune_level: must be 0..n_levels-2 with keep_top > 0", fi);
@@ -427,6 +436,11 @@ void fill_frame_dev(FrameDev &d, const pilot_frame &f, const pilot_result *r, in
     d.prune_level = f.prune_level;
     d.z_min = f.z_min;
     d.min_valid = f.min_valid;
+    d.adaptive = f.adaptive_priors ? 1 : 0;
+    d.alpha_ratio = f.alpha_ratio;
+    d.grav_gate = f.gravity_gate;
+    d.range_gate = f.range_gate;
+    d.cost_tol = f.cost_tol;
     d.poses_in = f.poses_in;
     d.prior_poses = f.prior_poses;
     d.prior_best = f.prior_best;
@@ -437,6 +451,7 @@ void fill_frame_dev(FrameDev &d, const pilot_frame &f, const pilot_result *r, in
         d.iters_out = r->iterations;
         d.status_out = r->status;
         d.best_out = r->best;
+        d.alpha_out = r->alpha;
     }
 }
 

@@ -99,8 +99,13 @@ class DeviceFrame:
         s.lambda_min_rel, s.lambda_max_rel = lm["lambda_min_rel"], lm["lambda_max_rel"]
         s.step_tol_t, s.step_tol_r, s.z_min = lm["step_tol_t"], lm["step_tol_r"], lm["z_min"]
         s.min_valid = int(lm["min_valid"])
+        s.cost_tol = float(lm.get("cost_tol", 0.0))
         s.keep_top = int(getattr(frame, "keep_top", 0))
         s.prune_level = int(getattr(frame, "prune_level", 0))
+        s.adaptive_priors = int(getattr(frame, "adaptive_priors", 0))
+        s.alpha_ratio = float(getattr(frame, "alpha_ratio", 0.0))
+        s.gravity_gate = float(getattr(frame, "gravity_gate", 0.0))
+        s.range_gate = float(getattr(frame, "range_gate", 0.0))
         self.s = s
 
     def _k(self, t: torch.Tensor) -> torch.Tensor:
@@ -122,13 +127,14 @@ class DeviceResult:
         self.iterations = torch.empty(M, dtype=torch.int32, device=device)
         self.status = torch.empty(M, dtype=torch.int32, device=device)
         self.best = torch.empty(1, dtype=torch.int32, device=device)
+        self.alpha = torch.empty((M, 2), dtype=torch.float64, device=device)
         self.s = A.Result(self.poses.data_ptr(), self.cost.data_ptr(), self.iterations.data_ptr(),
-                          self.status.data_ptr(), self.best.data_ptr())
+                          self.status.data_ptr(), self.best.data_ptr(), self.alpha.data_ptr())
 
     def numpy(self) -> dict:
         return dict(poses=self.poses.cpu().numpy(), cost=self.cost.cpu().numpy(),
                     iterations=self.iterations.cpu().numpy(), status=self.status.cpu().numpy(),
-                    best=int(self.best.cpu().item()))
+                    alpha=self.alpha.cpu().numpy(), best=int(self.best.cpu().item()))
 
 
 @dataclass

@@ -199,3 +199,48 @@ def test_tile_shapes_and_kernel_variants_match_oracle(tmp_path, variant, G):
     orc = oracle.solve(f, threads=8)
     rows, fails = compare_solutions(f, gpu, orc, POSE_TOL_M, POSE_TOL_DEG, f"v{variant}G{G}")
     assert not fails, fails
+
+
+# --------------------------------------------------------------------------- adaptive prior scales
+def _check_alpha(f, gpu, orc, rtol):
+    ok = (orc["status"] != oracle.DEGENERATE) & (gpu["status"] != oracle.DEGENERATE)
+    assert ok.any()
+    a, b = gpu["alpha"][ok], orc["alpha"][ok]
+    assert np.all(np.abs(a - b) <= rtol * np.abs(b)), np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300))
+    return b
+
+
+def test_adaptive_prior_scales_match_oracle(ctx):
+    """Scales set from gradient ratios at every level start, then held."""
+    f = pyramid_frame(seed=3)
+    f.adaptive_priors, f.alpha_ratio = 1, 0.05
+    say("adaptive prior scales, pyramid seed=3")
+    gpu = solve_gpu(ctx, f)
+    orc = oracle.solve(f, threads=8)
+    rows, fails = compare_solutions(f, gpu, orc, POSE_TOL_M, POSE_TOL_DEG, "adaptive")
+    assert not fails, fails
+    assert check_best(f, gpu, orc, POSE_TOL_M, POSE_TOL_DEG)
+    b = _check_alpha(f, gpu, orc, 1e-3)
+    assert np.any(b[:, 0] < f.lambda_imu) or np.any(b[:, 1] < f.lambda_range)     # the cap binds somewhere
+
+
+def test_fixed_scales_are_reported(ctx):
+    f = pyramid_frame(seed=4, M=5)
+    gpu = solve_gpu(ctx, f)
+    assert np.array_equal(gpu["alpha"], np.tile([f.lambda_imu, f.lambda_range], (5, 1)))
+
+
+def test_range_gate_with_a_corrupted_reading_matches_oracle(ctx):
+    f = S.make_frame(1, 0, noise=False)
+    f.lambda_range = 1.0
+    f.d_range += 40.0
+    f.adaptive_priors = 1
+    say("range gate, corrupted reading")
+    gpu = solve_gpu(ctx, f)
+    orc = oracle.solve(f, threads=8)
+    rows, fails = compare_solutions(f, gpu, orc, POSE_TOL_M, POSE_TOL_DEG, "gate")
+    assert not fails, fails
+    b = _check_alpha(f, gpu, orc, 1e-6)
+    assert b[0, 1] < 0.01 * f.lambda_range
+    te, _ = S.pose_errors(gpu["poses"][0], f.gt_pose)
+    assert te[0] < 0.5

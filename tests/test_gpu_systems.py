@@ -205,6 +205,9 @@ def test_abi_errors_launch_nothing(alone):
     bad.n_levels = 5
     expect(A.EINVAL, bad, "n_levels")
     bad = A.Frame.from_buffer_copy(base)
+    bad.adaptive_priors, bad.alpha_ratio = 1, float("nan")
+    expect(A.EINVAL, bad, "alpha_ratio")
+    bad = A.Frame.from_buffer_copy(base)
     bad.level[2].loss_scale = float("nan")
     expect(A.EINVAL, bad, "loss_scale")
     bad = A.Frame.from_buffer_copy(base)

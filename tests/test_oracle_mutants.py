@@ -37,6 +37,10 @@ MUTANTS = {
     "gravity_prior_weight": ("c += a_grav * rho;", "c += rho;"),
     "gate_not_squared": ("alpha[s] *= (gate[s] / rn) * (gate[s] / rn);", "alpha[s] *= (gate[s] / rn);"),
     "ratio_cap_direction": ("lam[s] * gn > f->alpha_ratio * gv", "lam[s] * gn < f->alpha_ratio * gv"),
+    "cost_tolerance_ignored": ("const int flat = f->cost_tol > 0.0 && fabs(cc - c) <= f->cost_tol * c;",
+                               "const int flat = 0;"),
+    "cost_tolerance_absolute": ("const int flat = f->cost_tol > 0.0 && fabs(cc - c) <= f->cost_tol * c;",
+                                "const int flat = f->cost_tol > 0.0 && fabs(cc - c) <= f->cost_tol;"),
     "scales_from_candidate_gradient": ("orc_prior_scales(f, st->T, g, st->alpha);",
                                        "orc_prior_scales(f, st->T, H, st->alpha);"),
 }

@@ -347,7 +347,7 @@ def test_noise_free_frames_converge_to_ground_truth():
 
 def test_accepted_costs_never_increase():
     f = S.make_frame(2, 3, N=400, M=6, level_shapes=((60, 80, 16), (120, 160, 32)), iters=(25, 25))
-    f.lm["step_tol_t"] = f.lm["step_tol_r"] = 0.0        # run every iteration
+    f.lm["step_tol_t"] = f.lm["step_tol_r"] = f.lm["cost_tol"] = 0.0      # run every iteration
     r = oracle.solve(f, threads=4, trace=True)
     tr = r["trace"]
     for m in range(tr.shape[0]):
@@ -513,7 +513,7 @@ def test_solve_reports_the_scales_of_the_level_start():
 
 def test_adaptive_accepted_costs_never_increase_within_a_level():
     f = S.make_frame(2, 3, N=400, M=6, level_shapes=((60, 80, 16), (120, 160, 32)), iters=(25, 25))
-    f.lm["step_tol_t"] = f.lm["step_tol_r"] = 0.0
+    f.lm["step_tol_t"] = f.lm["step_tol_r"] = f.lm["cost_tol"] = 0.0
     f.adaptive_priors, f.alpha_ratio = 1, 0.05
     r = oracle.solve(f, threads=4, trace=True)
     tr = r["trace"]
@@ -541,3 +541,30 @@ def test_gate_protects_against_a_corrupted_range_reading():
     assert e_vis < 1e-5
     assert e_fixed > 10.0, e_fixed                      # the bad reading wins at a fixed scale
     assert e_gated < 0.5 and e_gated < e_fixed / 50.0, (e_gated, e_fixed)
+
+
+# ---------------------------------------------------------------- LM stopping rules
+def test_cost_tolerance_stops_exactly_where_the_cost_goes_flat():
+    """With the function tolerance on, a level ends at the first candidate
+    whose cost is within cost_tol of the current cost and not before."""
+    f = S.make_frame(2, 3, N=400, M=6, level_shapes=((60, 80, 16), (120, 160, 32)), iters=(25, 25))
+    f.lm["step_tol_t"] = f.lm["step_tol_r"] = 0.0        # only the cost rule may stop a level
+    tol = f.lm["cost_tol"] = 1e-9
+    r = oracle.solve(f, threads=4, trace=True)
+    tr = r["trace"]
+    stopped = 0
+    for m in range(tr.shape[0]):
+        rows = tr[m][~np.isnan(tr[m][:, 0])]
+        for lvl in np.unique(rows[:, 0]):
+            R = rows[rows[:, 0] == lvl]
+            flat = np.abs(R[:, 2] - R[:, 1]) <= tol * R[:, 1]
+            assert not flat[:-1].any()                    # never ran past a flat candidate
+            stopped += bool(flat[-1])
+            if len(R) < f.levels[int(lvl)].iters:         # ended early: only the cost rule can do that
+                assert flat[-1] or r["status"][m] == oracle.STALLED
+    assert stopped > 0
+    # a huge tolerance ends every level at its first candidate
+    f.lm["cost_tol"] = 1.0
+    r = oracle.solve(f, threads=4)
+    ok = r["status"] != oracle.DEGENERATE
+    assert np.all(r["iterations"][ok] == len(f.levels)) and np.all(r["status"][ok] == oracle.CONVERGED)
