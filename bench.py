@@ -42,7 +42,7 @@ def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=None)
-    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--config", type=int, default=2, choices=[0, 1, 2, 3, 4, 5])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
@@ -160,30 +160,61 @@ def roofline_leg(args, dfs, steps):
 
 def cpu_leg(args, frames):
     """The FP64 oracle, as it stands, on a bounded sample of the workload:
-    whole hypotheses (they are independent), full N, every level."""
+    whole hypotheses (they are independent), full N, every level; on all
+    host threads, and a shorter single-thread run.  Returns the baseline
+    record and the oracle's results for the sampled hypotheses."""
     import numpy as np
 
     import oracle
     if args.no_cpu_baseline:
-        return None
+        return None, None
     f = frames[0]
+    Ns = [L.N for L in f.levels]
+
+    def evals(r, k):
+        ok = r["status"] != oracle.DEGENERATE
+        return int(k * sum(Ns) + np.sum(r["iterations"][ok]) * float(np.mean(Ns)))
+
     # size the sample from a one-hypothesis probe
     t0 = time.perf_counter()
-    oracle.solve(f, hyps=[0], threads=1)
+    r1 = oracle.solve(f, hyps=[0], threads=1)
     t1 = time.perf_counter() - t0
+    one_thread = evals(r1, 1) / t1
     th = oracle.threads(0)
     k = int(max(1, min(f.M, args.cpu_seconds / max(t1, 1e-3) * th)))
     hyps = np.arange(k)
     t0 = time.perf_counter()
     r = oracle.solve(f, hyps=hyps)
     dt = time.perf_counter() - t0
-    ok = r["status"] != 3
-    Ns = [L.N for L in f.levels]
-    pairs = int(k * sum(Ns) + np.sum(r["iterations"][ok]) * float(np.mean(Ns)))
-    log(f"cpu oracle: {pairs / dt:.4g} evals/s on {th} threads ({k} hypotheses, {dt:.1f} s)")
-    return {"value": pairs / dt, "unit": "evals/s", "cores": int(th), "kind": "oracle",
-            "sample": f"hypotheses 0..{k - 1} of frame 0 at full N, all levels; {pairs} evaluations "
-                      f"(level starts + iterations x N) in {dt:.1f} s"}
+    pairs = evals(r, k)
+    log(f"cpu oracle: {pairs / dt:.4g} evals/s on {th} threads ({k} hypotheses, {dt:.1f} s); "
+        f"{one_thread:.4g} evals/s on 1 thread")
+    return ({"value": pairs / dt, "unit": "evals/s", "cores": int(th), "kind": "oracle",
+             "sample": f"hypotheses 0..{k - 1} of frame 0 at full N, all levels; {pairs} evaluations "
+                       f"(level starts + iterations x N) in {dt:.1f} s",
+             "one_thread_evals_per_s": one_thread}, r)
+
+
+def vs_oracle(frame, gpu, orc):
+    """Pose difference of the GPU result from the oracle's on the hypotheses
+    the oracle solved: over hypotheses converged (within 1 m / 1 deg of the
+    truth) in both, and how many verdicts agree."""
+    import numpy as np
+
+    from synth import frames as S
+    idx = orc["index"]
+    tg, rg = S.pose_errors(gpu["poses"][idx], frame.gt_pose)
+    to, ro = S.pose_errors(orc["poses"], frame.gt_pose)
+    vg, vo = (tg <= 1.0) & (rg <= 1.0), (to <= 1.0) & (ro <= 1.0)
+    both = vg & vo
+    dt = np.array([S.pose_errors(gpu["poses"][i], orc["poses"][k])[0][0] for k, i in enumerate(idx)])
+    dr = np.array([S.pose_errors(gpu["poses"][i], orc["poses"][k])[1][0] for k, i in enumerate(idx)])
+    return {"hypotheses": int(len(idx)), "verdicts_agree": int(np.sum(vg == vo)),
+            "converged_in_both": int(both.sum()),
+            "max_m": float(dt[both].max()) if both.any() else None,
+            "median_m": float(np.median(dt[both])) if both.any() else None,
+            "max_deg": float(dr[both].max()) if both.any() else None,
+            "median_deg": float(np.median(dr[both])) if both.any() else None}
 
 
 def line(args, value, steps, warmup, ms, dtype, workload, extra):
@@ -239,7 +270,7 @@ def run_solve_config(args):
     log(f"generated {len(frames)} frame(s) in {time.perf_counter() - t:.1f}s")
     dfs = [DeviceFrame(f, dtype=dtype) for f in frames]
     torch.cuda.synchronize()
-    steps = args.steps or {0: 50, 1: 1000, 2: 20, 3: 10, 4: 5}[cfg]
+    steps = args.steps or {0: 50, 1: 1000, 2: 50, 3: 50, 4: 20}[cfg]
 
     ctx = make_context(args)
     tune_s = tune(ctx, args, dfs)
@@ -272,6 +303,7 @@ def run_solve_config(args):
         tune(bctx, args, [dfb])
         bwall, blat, bst, bres = timed_solves(bctx, [dfb], steps, args.warmup)
         bo = bres[0].numpy()
+        bf16_result = bo
         bte, bre = S.pose_errors(bo["poses"][bo["best"]], frames[0].gt_pose)
         bms = bwall * 1e3 / steps
         extra["bf16_same_workload"] = {
@@ -281,7 +313,14 @@ def run_solve_config(args):
             "best_pose_error_deg": float(bre[0])}
         log(f"bf16: {bms:.3f} ms/step ({ms / bms:.2f}x per solve)")
         bctx.close()
-    extra["cpu_baseline"] = cpu_leg(args, frames)
+    extra["cpu_baseline"], orc = cpu_leg(args, frames)
+    if orc is not None and getattr(frames[0], "keep_top", 0) and len(orc["index"]) < frames[0].M:
+        orc = None                   # a pruned subset ranks differently from the full set
+    if orc is not None:
+        extra["vs_oracle"] = {"f32" if dtype == "f32" else dtype: vs_oracle(frames[0], outs[0], orc)}
+        if cfg == 2 and not args.no_bf16:
+            extra["vs_oracle"]["bf16 (oracle on the f32 inputs)"] = vs_oracle(frames[0], bf16_result, orc)
+        log(f"vs oracle: {extra['vs_oracle']}")
     names = {0: "paper-shaped context: 1 frame, N=500 anchors, 1210-hypothesis grid (+-10 m, 2 m, yaw +-1..9 deg) "
                 "pruned to the top 128 after the coarse level, 3 levels 120x160 / 240x320 / 480x640 with C=32 f32, "
                 "2/3/4 iterations (the paper reports 43.82 ms for its optimizer on an RTX 5090; context only)",

@@ -952,7 +952,6 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
     res.status = res.iterations + M;
     res.best = res.status + M;
     unsigned long long pairs_saved[kStatClasses] = {0};
-    bool have_pairs = false;
 
     auto apply = [&](const TileConfig &tc) {
         for (const std::string &k : todo) ctx->tuned[k] = tc;
@@ -980,7 +979,6 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
                 rc = fail(ctx, PILOT_EDEVICE, "hipMemcpy of counters failed");
                 break;
             }
-            have_pairs = true;
         }
         // bring the clocks up (an idle GPU runs the first tens of ms slower)
         apply(heuristic_tile(ctx, frame->level[0].C, frame->level[0].dtype, frame->level[0].N, M));
@@ -1004,7 +1002,8 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
         for (size_t c = 0; c < cand.size() && rc == PILOT_OK; ++c)
             if (again[c]) rc = run(c);
     } while (false);
-    if (have_pairs && ctx->pairs.p) {
+    // put the counters back as they were (zero if the buffer did not exist yet)
+    if (ctx->pairs.p) {
         if (hipMemcpy(ctx->pairs.p, pairs_saved, sizeof pairs_saved, hipMemcpyHostToDevice) != hipSuccess && !rc)
             rc = fail(ctx, PILOT_EDEVICE, "hipMemcpy of counters failed");
     }
