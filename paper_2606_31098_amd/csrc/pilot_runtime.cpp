@@ -945,7 +945,7 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
     void *buf = nullptr;
     const size_t bytes = (size_t)M * (12 + 1) * sizeof(double) + (size_t)M * 2 * sizeof(int32_t) + 64;
     HIPCHK(ctx, hipMalloc(&buf, bytes));
-    pilot_result res;
+    pilot_result res{};                 // every pointer not set below stays NULL (optional outputs off)
     res.poses_out = (double *)buf;
     res.cost = res.poses_out + (size_t)M * 12;
     res.iterations = (int32_t *)(res.cost + M);
