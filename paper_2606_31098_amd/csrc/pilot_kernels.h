@@ -30,6 +30,10 @@ hipError_t launch_init(const FrameDev *frames, int n_frames, int max_M, HypState
                        PoseEval *pose, int *hlev, int mode, const double *diag_poses,
                        int diag_level, hipStream_t s);
 
+// Per-cell Gram matrices of the bilinear coefficients of a feature map
+// (pass kernel variant 3): 10 doubles per cell, cells y0 W + x0.
+hipError_t launch_gram(const void *feat, int H, int W, int C, int dtype, double *gram, hipStream_t s);
+
 // Geo-anchor lift and reference-descriptor sampling (see pilot_lift).
 hipError_t launch_lift(const float *dsm, int Hd, int Wd, double x0, double y0, double gsd, const float *uv, int N,
                        const void *ref_map, int Hr, int Wr, int C, int dtype, double scale, float *x, float *y,

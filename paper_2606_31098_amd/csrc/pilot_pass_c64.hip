@@ -1,7 +1,8 @@
-// Pass kernels for C = 64 channels (f32 and bf16; G = 4, 8, 16; two loop variants).
+// Pass kernels for C = 64 channels (f32 and bf16; G = 4, 8, 16; three kernel variants).
 #include "pilot_kernels.h"
 #include "pilot_pass.inc"
 #include "pilot_pass2.inc"
+#include "pilot_pass3.inc"
 
 namespace pilot {
 PILOT_INSTANTIATE_PASS(64)

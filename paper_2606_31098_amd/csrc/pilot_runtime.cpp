@@ -62,6 +62,13 @@ struct Plan {
     int total_hyps = 0, max_M = 0, max_levels = 0;
     size_t partial_floats = 0;
     std::string key;
+    // Gram tables of the (frame, level) pairs whose tiles use pass variant 3
+    struct GramJob {
+        int frame, level;
+        size_t offset;
+    };
+    std::vector<GramJob> gram_jobs;
+    size_t gram_bytes = 0;
 };
 
 struct TimedLaunch {
@@ -94,7 +101,7 @@ struct pilot_ctx {
     std::string err;
 
     // workspace
-    DevBuf desc, hs, pose, hlev, partials, pairs;
+    DevBuf desc, hs, pose, hlev, partials, pairs, gram;
     size_t ws_bytes = 0;
     unsigned generation = 0;
 
@@ -359,6 +366,15 @@ TileConfig choose_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M)
     return heuristic_tile(ctx, C, dtype, N, M);
 }
 
+// Serving slots have no Gram tables (a slot's maps are those of its frame,
+// admitted at any step): variant 3 runs as variant 1 with the same tile.
+TileConfig serving_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M)
+{
+    TileConfig tc = choose_tile(ctx, C, dtype, N, M);
+    if (tc.variant == 3) tc.variant = 1;
+    return tc;
+}
+
 int n_ptiles_of(const TileConfig &tc, int N)
 {
     const int P = (kBlock / tc.G) * tc.PPG;
@@ -507,6 +523,12 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
             g.passes = (only_level >= 0) ? 1 : 1 + iters;
             g.stat_class = class_index(l, g.C, g.dtype);
             g.tc.grid = grid_of(ctx, g.tc, g.n_items);
+            if (g.tc.variant == 3)
+                for (int i : kv.second) {
+                    const pilot_level &Li = frames[i].level[l];
+                    plan.gram_jobs.push_back(Plan::GramJob{i, l, plan.gram_bytes});
+                    plan.gram_bytes += ((size_t)Li.H * Li.W * 10 * sizeof(double) + 255) & ~(size_t)255;
+                }
             plan.partial_floats = std::max(plan.partial_floats, (size_t)g.n_items * g.tc.G * kNV);
             plan.groups.push_back(g);
             key << "|l" << l << "c" << g.C << "d" << g.dtype << "G" << g.tc.G << "p" << g.tc.PPG << "g" << g.tc.grid
@@ -560,9 +582,15 @@ int upload_plan(pilot_ctx *ctx, const Plan &plan, DevPtrs &dp)
     return PILOT_OK;
 }
 
-int ensure_state(pilot_ctx *ctx, const Plan &plan)
+// Workspace for a plan; points the plan's levels at their Gram tables.
+int ensure_state(pilot_ctx *ctx, Plan &plan)
 {
     int rc;
+    if (plan.gram_bytes) {
+        if ((rc = ensure(ctx, ctx->gram, plan.gram_bytes))) return rc;
+        for (const Plan::GramJob &j : plan.gram_jobs)
+            plan.frames[j.frame].lv[j.level].gram = (const double *)((const char *)ctx->gram.p + j.offset);
+    }
     const size_t H = std::max(1, plan.total_hyps);
     if ((rc = ensure(ctx, ctx->hs, H * sizeof(HypState)))) return rc;
     if ((rc = ensure(ctx, ctx->pose, H * sizeof(PoseEval)))) return rc;
@@ -576,6 +604,10 @@ int ensure_state(pilot_ctx *ctx, const Plan &plan)
 int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const LaunchGroup &g, int mode,
                  hipStream_t s, bool timed)
 {
+    if (g.tc.variant == 3)                     // every frame of the group needs its Gram table
+        for (int t = g.tile_off; t < g.tile_off + g.n_tiles; ++t)
+            if (!plan.frames[plan.tiles[t].frame].lv[g.level].gram)
+                return fail(ctx, PILOT_EDEVICE, "internal: pass variant 3 without a Gram table (level %d)", g.level);
     PassArgs a;
     a.frames = dp.frames;
     a.items = dp.items + g.item_off;
@@ -615,9 +647,21 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Laun
     return PILOT_OK;
 }
 
+// Gram tables of the plan's variant-3 levels (they depend on the feature
+// maps only, and are rebuilt with every solve since a replay may see new maps).
+int enqueue_gram(pilot_ctx *ctx, const Plan &plan, hipStream_t s)
+{
+    for (const Plan::GramJob &j : plan.gram_jobs) {
+        const LevelDev &L = plan.frames[j.frame].lv[j.level];
+        HIPCHK(ctx, launch_gram(L.feat, L.H, L.W, L.C, L.dtype, (double *)L.gram, s));
+    }
+    return PILOT_OK;
+}
+
 // The full LM schedule of a plan on stream s.
 int enqueue_schedule(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, hipStream_t s, bool timed)
 {
+    if (int rc = enqueue_gram(ctx, plan, s)) return rc;
     HIPCHK(ctx, launch_init(dp.frames, (int)plan.frames.size(), plan.max_M, (HypState *)ctx->hs.p,
                             (PoseEval *)ctx->pose.p, (int *)ctx->hlev.p, MODE_LM, nullptr, 0, s));
     for (int l = 0; l < plan.max_levels; ++l) {
@@ -648,7 +692,7 @@ void load_tune_cache(pilot_ctx *ctx)
     std::string key;
     TileConfig tc;
     while (in >> key >> tc.G >> tc.PPG >> tc.grid >> tc.variant)
-        if (pass_supported(16, 0, tc.G) && tc.PPG >= 1 && tc.PPG <= 64 && (tc.variant == 1 || tc.variant == 2))
+        if (pass_supported(16, 0, tc.G) && tc.PPG >= 1 && tc.PPG <= 64 && tc.variant >= 1 && tc.variant <= 3)
             ctx->tuned[key] = tc;
 }
 
@@ -743,7 +787,7 @@ void pilot_destroy(pilot_ctx *ctx)
         if (s.ev) hipEventSynchronize(s.ev), hipEventDestroy(s.ev);
         if (s.p) hipHostFree(s.p);
     }
-    for (DevBuf *b : {&ctx->desc, &ctx->hs, &ctx->pose, &ctx->hlev, &ctx->partials, &ctx->pairs,
+    for (DevBuf *b : {&ctx->desc, &ctx->hs, &ctx->pose, &ctx->hlev, &ctx->partials, &ctx->pairs, &ctx->gram,
                       &ctx->s_frames, &ctx->s_desc, &ctx->s_done})
         if (b->p) hipFree(b->p);
     for (auto &fb : ctx->flagbuf) {
@@ -850,6 +894,7 @@ int pilot_linearize(pilot_ctx *ctx, const pilot_frame *frame, int level, const d
     if ((rc = ensure_state(ctx, plan))) return rc;
     DevPtrs dp;
     if ((rc = upload_plan(ctx, plan, dp))) return rc;
+    if ((rc = enqueue_gram(ctx, plan, ctx->stream))) return rc;
     HIPCHK(ctx, launch_init(dp.frames, 1, plan.max_M, (HypState *)ctx->hs.p, (PoseEval *)ctx->pose.p,
                             (int *)ctx->hlev.p, MODE_DIAG, poses, level, ctx->stream));
     for (const LaunchGroup &g : plan.groups)
@@ -935,7 +980,7 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
     if ((rc = collect_timings(ctx))) return rc;           // earlier profiled launches go to the counters
 
     std::vector<TileConfig> cand;
-    for (int variant : {1, 2})
+    for (int variant : {1, 2, 3})
         for (int G : {4, 8, 16})
             for (int ppg : {2, 4, 8, 16})
                 for (int bpc : {0, 2, 4}) cand.push_back(TileConfig{G, ppg, bpc, variant});
@@ -1165,7 +1210,7 @@ int serving_rebuild(pilot_ctx *ctx)
         for (int k = 0; k < (int)frames.size(); ++k)
             if (l < frames[k].n_levels) {
                 const pilot_level &L = frames[k].level[l];
-                const TileConfig tc = choose_tile(ctx, L.C, L.dtype, L.N, frames[k].M);
+                const TileConfig tc = serving_tile(ctx, L.C, L.dtype, L.N, frames[k].M);
                 by_class[{L.C, L.dtype, tc.G, tc.PPG, tc.variant}].push_back(k);
             }
         for (auto &kv : by_class) {
@@ -1174,7 +1219,7 @@ int serving_rebuild(pilot_ctx *ctx)
             g.C = kv.first[0];
             g.dtype = kv.first[1];
             const pilot_level &L0 = frames[kv.second[0]].level[l];
-            g.tc = choose_tile(ctx, g.C, g.dtype, L0.N, frames[kv.second[0]].M);
+            g.tc = serving_tile(ctx, g.C, g.dtype, L0.N, frames[kv.second[0]].M);
             g.item_off = (int)plan.items.size();
             g.tile_off = (int)plan.tiles.size();
             for (int k : kv.second) {

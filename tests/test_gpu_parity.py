@@ -165,26 +165,35 @@ def _floor_log2(n):
     return max(int(n), 1).bit_length() - 1
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 @pytest.mark.parametrize("G", [4, 8, 16])
-def test_tile_shapes_and_kernel_variants_match_oracle(tmp_path, variant, G):
-    """Every lane-group width and both loop variants (forced through a tune
-    cache) reproduce the oracle's normal equations and solves."""
+def test_tile_shapes_and_kernel_variants_match_oracle(tmp_path, variant, G, dtype):
+    """Every lane-group width and every pass-kernel variant (forced through a
+    tune cache) reproduces the oracle's normal equations and solves (bf16: the
+    oracle runs on the same rounded maps and descriptors)."""
     from paper_2606_31098_amd.pilot import Context, DeviceFrame
-    f = pyramid_frame(seed=8, N=900, M=11, iters=(4, 4, 4))
+    d = 0 if dtype == "f32" else 1
+
+    def frame():
+        fr = pyramid_frame(seed=8, N=900, M=11, iters=(4, 4, 4))
+        return fr if dtype == "f32" else bf16_copy(fr)
+
+    f = frame()
     cache = tmp_path / "tune.txt"
     with open(cache, "w") as fh:
         for L in f.levels:
-            fh.write(f"C{L.C}_d0_N{_floor_log2(L.N)}_M{_floor_log2(f.M)}_v2 {G} 2 0 {variant}\n")
+            fh.write(f"C{L.C}_d{d}_N{_floor_log2(L.N)}_M{_floor_log2(f.M)}_v2 {G} 2 0 {variant}\n")
     c = Context(0, tune_cache=str(cache))
-    assert f"G={G}" in c.tile_choice(f.levels[0].C, 0, f.levels[0].N, f.M)
+    assert f"G={G}" in c.tile_choice(f.levels[0].C, d, f.levels[0].N, f.M)
+    assert f"V={variant}" in c.tile_choice(f.levels[0].C, d, f.levels[0].N, f.M)
     rng = np.random.default_rng(1)
     poses = np.stack([oracle.compose(oracle.se3_exp(np.concatenate([rng.normal(0, 2, 3), rng.normal(0, 0.02, 3)])),
                                      f.gt_pose) for _ in range(f.M)])
-    fm = mask_edges(pyramid_frame(seed=8, N=900, M=11, iters=(4, 4, 4)), poses)
-    df = DeviceFrame(fm)
+    fm = mask_edges(frame(), poses)
+    df = DeviceFrame(fm, dtype=dtype)
     of = oracle.OracleFrame(fm)
-    say(f"variant={variant} G={G}")
+    say(f"variant={variant} G={G} dtype={dtype}")
     for lvl in range(3):
         H21, g, cost, n = c.linearize(df, lvl, torch.as_tensor(poses, device="cuda"))
         torch.cuda.synchronize()
@@ -195,9 +204,9 @@ def test_tile_shapes_and_kernel_variants_match_oracle(tmp_path, variant, G):
             err = rel_frobenius(np.concatenate([H[m], g[m][:, None]], 1), np.concatenate([Ho, go[:, None]], 1))
             assert err <= NEQ_TOL, (lvl, m, err)
             assert abs(cost[m] - co) <= 1e-9 * abs(co), (lvl, m)
-    gpu = c.solve([DeviceFrame(f)])[0].numpy()
+    gpu = c.solve([DeviceFrame(f, dtype=dtype)])[0].numpy()
     orc = oracle.solve(f, threads=8)
-    rows, fails = compare_solutions(f, gpu, orc, POSE_TOL_M, POSE_TOL_DEG, f"v{variant}G{G}")
+    rows, fails = compare_solutions(f, gpu, orc, POSE_TOL_M, POSE_TOL_DEG, f"v{variant}G{G}{dtype}")
     assert not fails, fails
 
 
