@@ -116,7 +116,8 @@ def tune(ctx, args, dfs):
     if not args.no_tune:
         seen = set()
         for d in dfs:
-            key = tuple((L.C, L.dtype, L.N.bit_length(), d.M.bit_length()) for L in d.s.level[:d.s.n_levels])
+            key = tuple((L.C, L.dtype, L.N.bit_length(), d.M.bit_length(), (L.H * L.W).bit_length())
+                        for L in d.s.level[:d.s.n_levels])
             if key not in seen:
                 seen.add(key)
                 ctx.autotune(d)
@@ -244,8 +245,9 @@ def write_tiles(args):
     from synth import frames as S
     from synth import sequences as Q
     ctx = Context(0, tune_cache=args.tune_cache)
-    sets = [(c,) + config_frames(c, 0) for c in (0, 1, 2, 3, 4)]
+    sets = [(c,) + config_frames(c, 0) for c in (0, 1, 2)]
     sets.append((2, config_frames(2, 0)[0], "bf16"))
+    sets += [(c,) + config_frames(c, 0) for c in (3, 4)]
     serve = [S.make_frame(2, 0, N=side * side // 32, M=m, level_shapes=Q.LEVELS, iters=Q.ITERS, dsm_side=side)
              for side in (128, 256, 512) for m in (64, 128, 256, 512)]
     sets.append(("serving", serve, "bf16"))
@@ -274,7 +276,7 @@ def run_solve_config(args):
 
     ctx = make_context(args)
     tune_s = tune(ctx, args, dfs)
-    tiles = sorted({ctx.tile_choice(L.C, L.dtype, L.N, d.M) for d in dfs for L in d.s.level[:d.s.n_levels]})
+    tiles = sorted({ctx.tile_choice(L.C, L.dtype, L.N, d.M, L.H * L.W) for d in dfs for L in d.s.level[:d.s.n_levels]})
     log(f"tiles ({tune_s:.1f}s): {tiles[:6]}")
     wall, lat, st, res = timed_solves(ctx, dfs, steps, args.warmup)
     pairs = sum(st.pairs)

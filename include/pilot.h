@@ -282,8 +282,10 @@ int pilot_get_stats(pilot_ctx *ctx, pilot_stats *out, int reset);
  * per shape class and appended to the tune cache file. */
 int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame);
 
-/* "G=8 PPG=8 BPC=2" style description of the tile choice for a level shape. */
-int pilot_tile_choice(pilot_ctx *ctx, int C, int dtype, int N, int M, char *buf, int buflen);
+/* "G=8 PPG=8 BPC=2 V=3 tuned=1" style description of the tile choice for a
+ * level shape (C channels, dtype, N anchors, M hypotheses, HW = H*W map
+ * pixels). */
+int pilot_tile_choice(pilot_ctx *ctx, int C, int dtype, int N, int M, int64_t HW, char *buf, int buflen);
 
 int pilot_abi_version(void);
 

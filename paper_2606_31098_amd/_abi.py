@@ -103,7 +103,7 @@ def load(path: str = LIB_PATH):
                              _vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double, _vp, _vp, _vp, _vp]
     L.pilot_get_stats.argtypes = [_vp, P(Stats), C.c_int]
     L.pilot_autotune.argtypes = [_vp, P(Frame)]
-    L.pilot_tile_choice.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_char_p, C.c_int]
+    L.pilot_tile_choice.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_char_p, C.c_int]
     L.pilot_abi_version.restype = C.c_int
     L.pilot_sizeof.argtypes = [C.c_char_p]
     L.pilot_sizeof.restype = C.c_size_t

@@ -336,14 +336,17 @@ int log2_bucket(int n)
     return b;
 }
 
-std::string tune_key(int C, int dtype, int N, int M)
+// Tile-database key of a level shape: channels, dtype and log2 buckets of
+// the anchors, hypotheses and map pixels.
+std::string tune_key(int C, int dtype, int N, int M, long HW)
 {
     std::ostringstream o;
-    o << "C" << C << "_d" << dtype << "_N" << log2_bucket(N) << "_M" << log2_bucket(M) << "_v2";
+    o << "C" << C << "_d" << dtype << "_N" << log2_bucket(N) << "_M" << log2_bucket(M) << "_P"
+      << log2_bucket((int)std::min<long>(HW, 1L << 30)) << "_v3";
     return o.str();
 }
 
-TileConfig heuristic_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M)
+TileConfig heuristic_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M, long HW)
 {
     TileConfig tc;
     tc.G = (C >= 128) ? 8 : 4;      // measured: G = 4 up to C = 64, G = 8 at C = 128
@@ -359,18 +362,18 @@ TileConfig heuristic_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M)
     return tc;
 }
 
-TileConfig choose_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M)
+TileConfig choose_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M, long HW)
 {
-    auto it = ctx->tuned.find(tune_key(C, dtype, N, M));
+    auto it = ctx->tuned.find(tune_key(C, dtype, N, M, HW));
     if (it != ctx->tuned.end()) return it->second;
-    return heuristic_tile(ctx, C, dtype, N, M);
+    return heuristic_tile(ctx, C, dtype, N, M, HW);
 }
 
 // Serving slots have no Gram tables (a slot's maps are those of its frame,
 // admitted at any step): variant 3 runs as variant 1 with the same tile.
-TileConfig serving_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M)
+TileConfig serving_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M, long HW)
 {
-    TileConfig tc = choose_tile(ctx, C, dtype, N, M);
+    TileConfig tc = choose_tile(ctx, C, dtype, N, M, HW);
     if (tc.variant == 3) tc.variant = 1;
     return tc;
 }
@@ -495,7 +498,7 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
         for (int i = 0; i < n; ++i)
             if (l < frames[i].n_levels) {
                 const pilot_level &L = frames[i].level[l];
-                const TileConfig tc = choose_tile(ctx, L.C, L.dtype, L.N, frames[i].M);
+                const TileConfig tc = choose_tile(ctx, L.C, L.dtype, L.N, frames[i].M, (long)L.H * L.W);
                 by_class[{L.C, L.dtype, tc.G, tc.PPG, tc.variant}].push_back(i);
             }
         for (auto &kv : by_class) {
@@ -506,7 +509,7 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
             int iters = 0;
             for (int i : kv.second) iters = std::max(iters, frames[i].level[l].iters);
             const pilot_level &L0 = frames[kv.second[0]].level[l];
-            g.tc = choose_tile(ctx, g.C, g.dtype, L0.N, frames[kv.second[0]].M);
+            g.tc = choose_tile(ctx, g.C, g.dtype, L0.N, frames[kv.second[0]].M, (long)L0.H * L0.W);
             g.item_off = (int)plan.items.size();
             g.tile_off = (int)plan.tiles.size();
             for (int i : kv.second) {
@@ -823,7 +826,7 @@ int pilot_solve(pilot_ctx *ctx, const pilot_frame *frames, int n_frames, const p
             bool need = false;
             for (int l = 0; l < frames[i].n_levels; ++l) {
                 const pilot_level &L = frames[i].level[l];
-                if (!ctx->tuned.count(tune_key(L.C, L.dtype, L.N, frames[i].M))) need = true;
+                if (!ctx->tuned.count(tune_key(L.C, L.dtype, L.N, frames[i].M, (long)L.H * L.W))) need = true;
             }
             if (need) {
                 int rc = pilot_autotune(ctx, &frames[i]);
@@ -972,7 +975,7 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
     std::vector<std::string> todo;
     for (int l = 0; l < frame->n_levels; ++l) {
         const pilot_level &L = frame->level[l];
-        keys[l] = tune_key(L.C, L.dtype, L.N, frame->M);
+        keys[l] = tune_key(L.C, L.dtype, L.N, frame->M, (long)L.H * L.W);
         if (!ctx->tuned.count(keys[l]) && std::find(todo.begin(), todo.end(), keys[l]) == todo.end())
             todo.push_back(keys[l]);
     }
@@ -1026,7 +1029,8 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
             }
         }
         // bring the clocks up (an idle GPU runs the first tens of ms slower)
-        apply(heuristic_tile(ctx, frame->level[0].C, frame->level[0].dtype, frame->level[0].N, M));
+        apply(heuristic_tile(ctx, frame->level[0].C, frame->level[0].dtype, frame->level[0].N, M,
+                             (long)frame->level[0].H * frame->level[0].W));
         double warm = 0.0;
         for (int k = 0; k < 50 && warm < 40.0 && rc == PILOT_OK; ++k) {
             double ms[PILOT_MAX_LEVELS];
@@ -1070,12 +1074,12 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
     return PILOT_OK;
 }
 
-int pilot_tile_choice(pilot_ctx *ctx, int C, int dtype, int N, int M, char *buf, int buflen)
+int pilot_tile_choice(pilot_ctx *ctx, int C, int dtype, int N, int M, int64_t HW, char *buf, int buflen)
 {
     if (!ctx || !buf || buflen < 1) return fail(ctx, PILOT_EINVAL, "ctx/buf: invalid");
-    TileConfig tc = choose_tile(ctx, C, dtype, N, M);
+    TileConfig tc = choose_tile(ctx, C, dtype, N, M, (long)HW);
     snprintf(buf, buflen, "G=%d PPG=%d BPC=%d V=%d tuned=%d", tc.G, tc.PPG, tc.grid, tc.variant,
-             (int)ctx->tuned.count(tune_key(C, dtype, N, M)));
+             (int)ctx->tuned.count(tune_key(C, dtype, N, M, (long)HW)));
     return PILOT_OK;
 }
 
@@ -1133,7 +1137,7 @@ size_t frame_cost(const pilot_ctx *ctx, const pilot_frame &f)
         in += (size_t)L.H * L.W * L.C * es + (size_t)L.N * (3 * sizeof(float) + L.C * es);
         if (L.qconf) in += (size_t)L.H * L.W * sizeof(float);
         if (L.ref_w) in += (size_t)L.N * sizeof(float);
-        const TileConfig tc = choose_tile(ctx, L.C, L.dtype, L.N, f.M);
+        const TileConfig tc = choose_tile(ctx, L.C, L.dtype, L.N, f.M, (long)L.H * L.W);
         const size_t items = (size_t)((f.M + tc.G - 1) / tc.G) * n_ptiles_of(tc, L.N);
         part = std::max(part, items * tc.G * kNV * sizeof(float));
     }
@@ -1210,7 +1214,7 @@ int serving_rebuild(pilot_ctx *ctx)
         for (int k = 0; k < (int)frames.size(); ++k)
             if (l < frames[k].n_levels) {
                 const pilot_level &L = frames[k].level[l];
-                const TileConfig tc = serving_tile(ctx, L.C, L.dtype, L.N, frames[k].M);
+                const TileConfig tc = serving_tile(ctx, L.C, L.dtype, L.N, frames[k].M, (long)L.H * L.W);
                 by_class[{L.C, L.dtype, tc.G, tc.PPG, tc.variant}].push_back(k);
             }
         for (auto &kv : by_class) {
@@ -1219,7 +1223,7 @@ int serving_rebuild(pilot_ctx *ctx)
             g.C = kv.first[0];
             g.dtype = kv.first[1];
             const pilot_level &L0 = frames[kv.second[0]].level[l];
-            g.tc = serving_tile(ctx, g.C, g.dtype, L0.N, frames[kv.second[0]].M);
+            g.tc = serving_tile(ctx, g.C, g.dtype, L0.N, frames[kv.second[0]].M, (long)L0.H * L0.W);
             g.item_off = (int)plan.items.size();
             g.tile_off = (int)plan.tiles.size();
             for (int k : kv.second) {

@@ -235,9 +235,9 @@ class Context:
     def autotune(self, frame: DeviceFrame):
         self._check(self.lib.pilot_autotune(self.h, C.byref(frame.s)))
 
-    def tile_choice(self, C_: int, dtype: int, N: int, M: int) -> str:
+    def tile_choice(self, C_: int, dtype: int, N: int, M: int, HW: int) -> str:
         buf = C.create_string_buffer(128)
-        self._check(self.lib.pilot_tile_choice(self.h, C_, dtype, N, M, buf, 128))
+        self._check(self.lib.pilot_tile_choice(self.h, C_, dtype, N, M, HW, buf, 128))
         return buf.value.decode()
 
     def stats(self, reset: bool = False) -> Stats:

@@ -183,10 +183,12 @@ def test_tile_shapes_and_kernel_variants_match_oracle(tmp_path, variant, G, dtyp
     cache = tmp_path / "tune.txt"
     with open(cache, "w") as fh:
         for L in f.levels:
-            fh.write(f"C{L.C}_d{d}_N{_floor_log2(L.N)}_M{_floor_log2(f.M)}_v2 {G} 2 0 {variant}\n")
+            fh.write(f"C{L.C}_d{d}_N{_floor_log2(L.N)}_M{_floor_log2(f.M)}_P{_floor_log2(L.H * L.W)}_v3 "
+                     f"{G} 2 0 {variant}\n")
     c = Context(0, tune_cache=str(cache))
-    assert f"G={G}" in c.tile_choice(f.levels[0].C, d, f.levels[0].N, f.M)
-    assert f"V={variant}" in c.tile_choice(f.levels[0].C, d, f.levels[0].N, f.M)
+    L0 = f.levels[0]
+    assert f"G={G}" in c.tile_choice(L0.C, d, L0.N, f.M, L0.H * L0.W)
+    assert f"V={variant}" in c.tile_choice(L0.C, d, L0.N, f.M, L0.H * L0.W)
     rng = np.random.default_rng(1)
     poses = np.stack([oracle.compose(oracle.se3_exp(np.concatenate([rng.normal(0, 2, 3), rng.normal(0, 0.02, 3)])),
                                      f.gt_pose) for _ in range(f.M)])

@@ -307,14 +307,15 @@ def test_autotune_writes_every_level_key_and_stays_correct(tmp_path):
     st1 = ctx.stats(reset=False)
     assert sum(st1.pairs) == sum(st0.pairs) and sum(st1.launches) == sum(st0.launches)   # counters untouched
     lines = [ln.split() for ln in cache.read_text().splitlines()]
-    keys = {f"C{L.C}_d0_N{int(math.floor(math.log2(L.N)))}_M{int(math.floor(math.log2(f.M)))}_v2" for L in f.levels}
+    keys = {f"C{L.C}_d0_N{int(math.floor(math.log2(L.N)))}_M{int(math.floor(math.log2(f.M)))}"
+            f"_P{int(math.floor(math.log2(L.H * L.W)))}_v3" for L in f.levels}
     assert {ln[0] for ln in lines} == keys and len(lines) == len(keys)
     for ln in lines:
         G, ppg, bpc, var = map(int, ln[1:])
-        assert G in (4, 8, 16) and ppg in (2, 4, 8, 16) and bpc in (0, 2, 4) and var in (1, 2)
+        assert G in (4, 8, 16) and ppg in (2, 4, 8, 16) and bpc in (0, 2, 4) and var in (1, 2, 3)
     ctx2 = Context(0, tune_cache=str(cache))
     for L in f.levels:
-        assert "tuned=1" in ctx2.tile_choice(L.C, 0, L.N, f.M)
+        assert "tuned=1" in ctx2.tile_choice(L.C, 0, L.N, f.M, L.H * L.W)
     out = ctx2.solve([d])[0].numpy()
     torch.cuda.synchronize()
     rows, fails = compare_solutions(f, out, oracle.solve(f, threads=8), POSE_TOL_M, POSE_TOL_DEG, "tuned")
