@@ -143,7 +143,7 @@ def roofline_leg(args, dfs, steps):
         try:
             tj = json.load(open(TRAFFIC_FILE))
             entry = tj.get(f"config{args.config}")
-            if entry and entry.get("source_digest") == B.source_digest():
+            if entry and entry.get("pass_kernel_digest") == B.pass_kernel_digest():
                 traffic = entry.get("bytes_per_launch")
         except (OSError, ValueError):
             traffic = None

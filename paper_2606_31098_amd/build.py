@@ -46,6 +46,19 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
+def pass_kernel_digest() -> str:
+    """SHA-256 over the sources the pass kernels are compiled from (their
+    translation units and everything those include)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if (f.startswith("pilot_pass") and f.endswith((".hip", ".inc"))) or \
+                f in ("pilot_kernels.h", "pilot_lm.h", "pilot_device.h"):
+            h.update(f.encode())
+            h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
     cmd = [_hipcc(), *HIP_FLAGS, "-c", src, "-o", obj]
