@@ -476,7 +476,9 @@ def run_serving_config(args, worlds):
                          "max_active": st.max_active, "eagain": st.eagain,
                          "pose_error_m": {"median": float(np.median(te)), "p90": float(np.percentile(te, 90))},
                          "pose_error_deg": {"median": float(np.median(re_)), "p90": float(np.percentile(re_, 90))},
-                         "within_1m_1deg": float(np.mean((te <= 1) & (re_ <= 1)))},
+                         "within_1m_1deg": float(np.mean((te <= 1) & (re_ <= 1))),
+                         "host_seconds": {"prepare": st.host_prepare, "admit": st.host_admit,
+                                          "step": st.host_step, "poll": st.host_poll}},
              "gb_per_s_algorithmic": sum(counters.pair_bytes) / st.wall / 1e9,
              "roofline": None, "cpu_baseline": None}
     ctx.close()

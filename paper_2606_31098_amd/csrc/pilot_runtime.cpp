@@ -83,6 +83,8 @@ struct ServingSlot {
     size_t bytes = 0;
     uint64_t admit_step = 0;
     pilot_frame frame;
+    FrameDev dev{};      // host copy of the slot's device descriptor
+    DevBuf gram;         // Gram tables of the slot's variant-3 levels (kept for reuse)
 };
 
 constexpr int kFlagRing = 4;
@@ -369,13 +371,16 @@ TileConfig choose_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M, lon
     return heuristic_tile(ctx, C, dtype, N, M, HW);
 }
 
-// Serving slots have no Gram tables (a slot's maps are those of its frame,
-// admitted at any step): variant 3 runs as variant 1 with the same tile.
+// Serving slots use the same tiles as solves (a slot's Gram tables are built
+// when its frame is admitted).
 TileConfig serving_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M, long HW)
 {
-    TileConfig tc = choose_tile(ctx, C, dtype, N, M, HW);
-    if (tc.variant == 3) tc.variant = 1;
-    return tc;
+    return choose_tile(ctx, C, dtype, N, M, HW);
+}
+
+size_t gram_table_bytes(const pilot_level &L)
+{
+    return ((size_t)L.H * L.W * 10 * sizeof(double) + 255) & ~(size_t)255;
 }
 
 int n_ptiles_of(const TileConfig &tc, int N)
@@ -797,6 +802,8 @@ void pilot_destroy(pilot_ctx *ctx)
         if (fb.ev) hipEventDestroy(fb.ev);
         if (fb.host) hipHostFree(fb.host);
     }
+    for (ServingSlot &sl : ctx->slots)
+        if (sl.gram.p) hipFree(sl.gram.p);
     if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     delete ctx;
 }
@@ -1138,6 +1145,7 @@ size_t frame_cost(const pilot_ctx *ctx, const pilot_frame &f)
         if (L.qconf) in += (size_t)L.H * L.W * sizeof(float);
         if (L.ref_w) in += (size_t)L.N * sizeof(float);
         const TileConfig tc = choose_tile(ctx, L.C, L.dtype, L.N, f.M, (long)L.H * L.W);
+        if (tc.variant == 3) in += gram_table_bytes(L);
         const size_t items = (size_t)((f.M + tc.G - 1) / tc.G) * n_ptiles_of(tc, L.N);
         part = std::max(part, items * tc.G * kNV * sizeof(float));
     }
@@ -1202,6 +1210,9 @@ int serving_rebuild(pilot_ctx *ctx)
 {
     Plan &plan = ctx->serv_plan;
     plan = Plan();
+    plan.frames.assign(ctx->slots.size(), FrameDev{});     // indexed by slot (host copies, for checks)
+    for (int i = 0; i < (int)ctx->slots.size(); ++i)
+        if (ctx->slots[i].active) plan.frames[i] = ctx->slots[i].dev;
     std::vector<pilot_frame> frames;
     std::vector<int> slot_of;
     for (int i = 0; i < (int)ctx->slots.size(); ++i)
@@ -1304,6 +1315,26 @@ int pilot_admit(pilot_ctx *ctx, const pilot_frame *frame, const pilot_result *re
     fill_frame_dev(d, *frame, result, base);
     d.slot = s;
     d.done_flag = (int *)ctx->s_done.p + s;
+    // Gram tables of the levels whose tiles use pass variant 3, in the slot's own buffer
+    ServingSlot &sl = ctx->slots[s];
+    size_t gbytes = 0, goff[PILOT_MAX_LEVELS] = {0};
+    bool gneed[PILOT_MAX_LEVELS] = {false};
+    for (int l = 0; l < frame->n_levels; ++l) {
+        const pilot_level &L = frame->level[l];
+        if (serving_tile(ctx, L.C, L.dtype, L.N, frame->M, (long)L.H * L.W).variant == 3) {
+            gneed[l] = true;
+            goff[l] = gbytes;
+            gbytes += gram_table_bytes(L);
+        }
+    }
+    if (gbytes) {
+        if ((rc = ensure(ctx, sl.gram, gbytes, false, false))) {
+            arena_release(ctx, base, frame->M);
+            return rc;
+        }
+        for (int l = 0; l < frame->n_levels; ++l)
+            if (gneed[l]) d.lv[l].gram = (const double *)((const char *)sl.gram.p + goff[l]);
+    }
     int which;
     char *h = (char *)stage_acquire(ctx, sizeof(FrameDev), &which, &rc);
     if (!h) {
@@ -1317,7 +1348,12 @@ int pilot_admit(pilot_ctx *ctx, const pilot_frame *frame, const pilot_result *re
     ctx->stage[which].pending = true;
     HIPCHK(ctx, launch_init(dst, 1, frame->M, (HypState *)ctx->hs.p, (PoseEval *)ctx->pose.p, (int *)ctx->hlev.p,
                             MODE_LM, nullptr, 0, ctx->stream));
-    ServingSlot &sl = ctx->slots[s];
+    for (int l = 0; l < frame->n_levels; ++l)
+        if (gneed[l]) {
+            const pilot_level &L = frame->level[l];
+            HIPCHK(ctx, launch_gram(L.feat, L.H, L.W, L.C, L.dtype, (double *)d.lv[l].gram, ctx->stream));
+        }
+    sl.dev = d;
     sl.active = true;
     sl.M = frame->M;
     sl.hyp_base = base;

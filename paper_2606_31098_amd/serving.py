@@ -52,6 +52,12 @@ class RunStats:
     max_queue: int = 0
     wall: float = 0.0
     last_arrival: float = 0.0
+    # host seconds spent building frames, admitting, enqueueing steps
+    # (includes waiting for the step two back) and polling
+    host_prepare: float = 0.0
+    host_admit: float = 0.0
+    host_step: float = 0.0
+    host_poll: float = 0.0
 
 
 class ServingLoop:
@@ -81,8 +87,12 @@ class ServingLoop:
             heads = sorted((q[0].t_arrival, s) for s, q in queues.items() if q and not busy[s])
             for _, s in heads:
                 req = queues[s][0]
+                t1 = self.clock()
                 df, res, keep = req.prepare(prev.get(s))
+                t2 = self.clock()
                 slot = self.ctx.admit(df, res)
+                st.host_prepare += t2 - t1
+                st.host_admit += self.clock() - t2
                 if slot is None:
                     st.eagain += 1
                     break                               # no slot or budget: retry after the next pass
@@ -91,19 +101,23 @@ class ServingLoop:
                 active[slot] = (req, df, res, keep, self.clock() - t0, st.steps)
             st.max_active = max(st.max_active, len(active))
             if active:
+                t1 = self.clock()
                 self.ctx.step()
+                st.host_step += self.clock() - t1
                 st.steps += 1
             elif nxt < len(reqs) and realtime:
                 time.sleep(max(0.0, min(reqs[nxt].t_arrival - (self.clock() - t0), 0.002)))
-            for slot in list(active):
-                if self.ctx.poll(slot):
-                    req, df, res, keep, t_adm, s0 = active.pop(slot)
-                    c = Completion(req, t_adm, self.clock() - t0, res, st.steps - s0)
-                    st.completions.append(c)
-                    busy[req.stream] = False
-                    prev[req.stream] = res
-                    if on_complete:
-                        on_complete(c)
+            t1 = self.clock()
+            done = [slot for slot in list(active) if self.ctx.poll(slot)]
+            st.host_poll += self.clock() - t1
+            for slot in done:
+                req, df, res, keep, t_adm, s0 = active.pop(slot)
+                c = Completion(req, t_adm, self.clock() - t0, res, st.steps - s0)
+                st.completions.append(c)
+                busy[req.stream] = False
+                prev[req.stream] = res
+                if on_complete:
+                    on_complete(c)
             if not active and not any(queues.values()) and nxt >= len(reqs):
                 break
             if active and not realtime:

@@ -320,3 +320,47 @@ def test_autotune_writes_every_level_key_and_stays_correct(tmp_path):
     torch.cuda.synchronize()
     rows, fails = compare_solutions(f, out, oracle.solve(f, threads=8), POSE_TOL_M, POSE_TOL_DEG, "tuned")
     assert not fails, fails
+
+
+def test_serving_with_gram_tables_matches_solves(alone, tmp_path):
+    """Serving slots whose tiles use pass variant 3 build their Gram tables at
+    admission; their results equal those of solves with the same tiles,
+    bitwise, with frames arriving while others are in flight."""
+    from paper_2606_31098_amd.pilot import Context, DeviceResult
+    fr, dfs, _ = alone
+    cache = tmp_path / "tiles.txt"
+    with open(cache, "w") as fh:
+        for f in fr:
+            for L in f.levels:
+                fh.write(f"C{L.C}_d0_N{int(math.floor(math.log2(L.N)))}_M{int(math.floor(math.log2(f.M)))}"
+                         f"_P{int(math.floor(math.log2(L.H * L.W)))}_v3 4 2 0 3\n")
+    solo = Context(0, tune_cache=str(cache))
+    assert "V=3" in solo.tile_choice(fr[0].levels[0].C, 0, fr[0].levels[0].N, fr[0].M,
+                                     fr[0].levels[0].H * fr[0].levels[0].W)
+    ref = [as_np(solo.solve([d])[0]) for d in dfs]
+    torch.cuda.synchronize()
+    ctx = Context(0, max_slots=3, tune_cache=str(cache))
+    results = [DeviceResult(d.M) for d in dfs]
+    slot_of, done, arrived = {}, set(), []
+    schedule = {0: [0, 1], 3: [2], 4: [3]}
+    step = 0
+    say("serving with variant-3 tiles")
+    while len(done) < len(dfs):
+        arrived += schedule.get(step, [])
+        for i in list(arrived):
+            s = ctx.admit(dfs[i], results[i])
+            if s is None:
+                continue
+            slot_of[i] = s
+            arrived.remove(i)
+        ctx.step()
+        ctx.sync()
+        for i, s in list(slot_of.items()):
+            if ctx.poll(s):
+                done.add(i)
+                del slot_of[i]
+        step += 1
+        assert step < 400, "serving did not drain"
+    torch.cuda.synchronize()
+    for i in range(len(dfs)):
+        assert same(as_np(results[i]), ref[i]), i
