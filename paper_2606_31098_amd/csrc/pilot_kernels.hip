@@ -36,9 +36,14 @@ constexpr int kMaxG = 16;
 // in item order (fixed, independent of what else shares the launch), then
 // one thread per hypothesis adds the prior terms and advances its LM state
 // (or writes the diagnostic system).
-__global__ __launch_bounds__(256) void epilogue_kernel(EpilogueArgs e)
+constexpr int kEpiThreads = 512;
+
+__global__ __launch_bounds__(kEpiThreads) void epilogue_kernel(EpilogueArgs e)
 {
     __shared__ double s_sum[kMaxG][kNV];
+    __shared__ double s_part[kEpiThreads];
+    __shared__ HypState s_hs[kMaxG];
+    __shared__ PoseEval s_pe[kMaxG];
     const TileItem ti = e.tiles[blockIdx.x];
     const FrameDev *f = e.frames + ti.frame;
     const int G = e.G;
@@ -48,40 +53,56 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpilogueArgs e)
     unsigned act = 0;
     for (int hh = 0; hh < nh; ++hh) act |= (e.hlev[hb + hh] == e.level ? 1u : 0u) << hh;
     if (act == 0) return;
+    // R threads per value: thread (r, t) sums the items r, r + R, r + 2R, ...
+    // of value t (eight interleaved accumulators, so eight loads are in
+    // flight), then the R partial sums are added in r order: a fixed order
+    // for a given tile shape
     const int stride = G * kNV;
-    for (int t = threadIdx.x; t < stride; t += blockDim.x) {
-        const int hh = t / kNV, v = t - hh * kNV;
-        const float *src = e.partials + (size_t)ti.first_item * stride + t;
-        double s = 0.0;
-        // four interleaved accumulators (fixed order) keep four loads in flight
+    const int R = kEpiThreads / stride;
+    const int tv = threadIdx.x % stride, r = threadIdx.x / stride;
+    {
+        const int v = tv % kNV;
+        const float *src = e.partials + (size_t)ti.first_item * stride + tv;
         const int n = ti.n_ptiles;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        if (v < kNSum) {
-            int it = 0;
-            for (; it + 4 <= n; it += 4) {
-                s0 += (double)src[(size_t)it * stride];
-                s1 += (double)src[(size_t)(it + 1) * stride];
-                s2 += (double)src[(size_t)(it + 2) * stride];
-                s3 += (double)src[(size_t)(it + 3) * stride];
+        double a[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a[k] = 0.0;
+        if (r < R) {
+            if (v < kNSum) {
+                int it = r;
+                for (; it + 7 * R < n; it += 8 * R) {
+                    float x[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) x[k] = src[(size_t)(it + k * R) * stride];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) a[k] += (double)x[k];
+                }
+                for (; it < n; it += R) a[0] += (double)src[(size_t)it * stride];
+            } else if (v == kCostSlot) {
+                auto cost_at = [&](int i) {
+                    const float *q = src + (size_t)i * stride;
+                    const unsigned long long bits = (unsigned long long)__float_as_uint(q[0]) |
+                                                    ((unsigned long long)__float_as_uint(q[1]) << 32);
+                    return __longlong_as_double((long long)bits);
+                };
+                int it = r;
+                for (; it + 7 * R < n; it += 8 * R) {
+                    double x[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) x[k] = cost_at(it + k * R);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) a[k] += x[k];
+                }
+                for (; it < n; it += R) a[0] += cost_at(it);
             }
-            for (; it < n; ++it) s0 += (double)src[(size_t)it * stride];
-        } else if (v == kCostSlot) {
-            auto cost_at = [&](int it) {
-                const float *q = src + (size_t)it * stride;
-                const unsigned long long bits = (unsigned long long)__float_as_uint(q[0]) |
-                                                ((unsigned long long)__float_as_uint(q[1]) << 32);
-                return __longlong_as_double((long long)bits);
-            };
-            int it = 0;
-            for (; it + 4 <= n; it += 4) {
-                s0 += cost_at(it);
-                s1 += cost_at(it + 1);
-                s2 += cost_at(it + 2);
-                s3 += cost_at(it + 3);
-            }
-            for (; it < n; ++it) s0 += cost_at(it);
+            s_part[r * stride + tv] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         }
-        s = (s0 + s1) + (s2 + s3);
+    }
+    __syncthreads();
+    if (threadIdx.x < stride) {
+        const int hh = tv / kNV, v = tv - hh * kNV;
+        double s = 0.0;
+        for (int q = 0; q < R; ++q) s += s_part[q * stride + tv];
         s_sum[hh][v] = s;
     }
     __syncthreads();
@@ -104,8 +125,12 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpilogueArgs e)
         f->diag_n[m] = (int)S[27];
         e.hlev[gh] = -1;
     } else {
-        HypState s = e.hs[gh];
-        PoseEval p = e.pose[gh];
+        // the LM state lives in LDS while it is updated (a register copy of
+        // the whole state would not fit beside the reduction's registers)
+        HypState &s = s_hs[t];
+        PoseEval &p = s_pe[t];
+        s = e.hs[gh];
+        p = e.pose[gh];
         int hl = e.level;
         lm_advance(*f, s, S, p, hl);
         e.hs[gh] = s;
@@ -118,7 +143,7 @@ hipError_t launch_epilogue(const EpilogueArgs &e, hipStream_t s)
 {
     if (e.G > kMaxG) return hipErrorInvalidValue;
     if (e.n_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(epilogue_kernel, dim3(e.n_tiles), dim3(256), 0, s, e);
+    hipLaunchKernelGGL(epilogue_kernel, dim3(e.n_tiles), dim3(kEpiThreads), 0, s, e);
     return hipGetLastError();
 }
 
