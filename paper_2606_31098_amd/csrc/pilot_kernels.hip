@@ -334,7 +334,7 @@ hipError_t launch_prune(const FrameDev *frames, int n_frames, HypState *hs, Pose
 }
 
 // ------------------------------------------------------------------ Gram tables
-// One thread per cell (x0, y0), x0 <= W-2, y0 <= H-2: with the cell's taps in
+// Per cell (x0, y0), x0 <= W-2, y0 <= H-2: with the cell's taps in
 // the bilinear coefficient basis c = (t00, t10 - t00, t01 - t00,
 // t11 - t10 - t01 + t00), K = sum over channels of c c^T, upper triangle row
 // by row, in FP64 (products of two f32 or bf16 values are exact in FP64).
@@ -353,48 +353,77 @@ __device__ inline void load4(const void *base, size_t off, double out[4])
     }
 }
 
+// sum over the 4 lanes of an aligned lane quad (DPP quad permutes)
+__device__ __forceinline__ double quad_sum(double v)
+{
+    auto perm = [](double x, int ctrl) {
+        const long long b = __double_as_longlong(x);
+        int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+        if (ctrl == 0) {
+            lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
+        } else {
+            lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
+        }
+        return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+    };
+    v += perm(v, 0);
+    v += perm(v, 1);
+    return v;
+}
+
+// A lane quad per cell: lane q of the quad takes channels 4q + 16k .. +3, so
+// the quad's loads of one tap are one contiguous 64-byte run.
 template <int DT>
 __global__ __launch_bounds__(256) void gram_kernel(const void *feat, int H, int W, int C, double *gram)
 {
-    const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= (long)H * W) return;
-    const int y0 = (int)(cell / W), x0 = (int)(cell - (long)y0 * W);
-    if (x0 > W - 2 || y0 > H - 2) return;          // no cell starts on the last row or column
+    const long cell = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+    const int q = threadIdx.x & 3;
+    const bool live = cell < (long)H * W;
+    const int y0 = live ? (int)(cell / W) : 0, x0 = live ? (int)(cell - (long)y0 * W) : 0;
+    const bool work = live && x0 <= W - 2 && y0 <= H - 2;   // no cell starts on the last row or column
     double k[10];
 #pragma unroll
     for (int i = 0; i < 10; ++i) k[i] = 0.0;
-    const size_t o = (size_t)cell * C, oW = o + (size_t)W * C;
-    for (int c = 0; c < C; c += 4) {
-        double t0[4], t1[4], t2[4], t3[4];
-        load4<DT>(feat, o + c, t0);
-        load4<DT>(feat, o + C + c, t1);
-        load4<DT>(feat, oW + c, t2);
-        load4<DT>(feat, oW + C + c, t3);
+    if (work) {
+        const size_t o = (size_t)cell * C, oW = o + (size_t)W * C;
+        for (int c = 4 * q; c < C; c += 16) {
+            double t0[4], t1[4], t2[4], t3[4];
+            load4<DT>(feat, o + c, t0);
+            load4<DT>(feat, o + C + c, t1);
+            load4<DT>(feat, oW + c, t2);
+            load4<DT>(feat, oW + C + c, t3);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const double c0 = t0[e], c1 = t1[e] - t0[e], c2 = t2[e] - t0[e], c3 = (t3[e] - t2[e]) - c1;
-            k[0] = fma(c0, c0, k[0]);
-            k[1] = fma(c0, c1, k[1]);
-            k[2] = fma(c0, c2, k[2]);
-            k[3] = fma(c0, c3, k[3]);
-            k[4] = fma(c1, c1, k[4]);
-            k[5] = fma(c1, c2, k[5]);
-            k[6] = fma(c1, c3, k[6]);
-            k[7] = fma(c2, c2, k[7]);
-            k[8] = fma(c2, c3, k[8]);
-            k[9] = fma(c3, c3, k[9]);
+            for (int e = 0; e < 4; ++e) {
+                const double c0 = t0[e], c1 = t1[e] - t0[e], c2 = t2[e] - t0[e], c3 = (t3[e] - t2[e]) - c1;
+                k[0] = fma(c0, c0, k[0]);
+                k[1] = fma(c0, c1, k[1]);
+                k[2] = fma(c0, c2, k[2]);
+                k[3] = fma(c0, c3, k[3]);
+                k[4] = fma(c1, c1, k[4]);
+                k[5] = fma(c1, c2, k[5]);
+                k[6] = fma(c1, c3, k[6]);
+                k[7] = fma(c2, c2, k[7]);
+                k[8] = fma(c2, c3, k[8]);
+                k[9] = fma(c3, c3, k[9]);
+            }
         }
     }
-    double *out = gram + (size_t)10 * cell;
+    // every lane of the wave takes part in the quad sums (inactive cells add zeros)
 #pragma unroll
-    for (int i = 0; i < 10; ++i) out[i] = k[i];
+    for (int i = 0; i < 10; ++i) k[i] = quad_sum(k[i]);
+    if (work) {
+        double *out = gram + (size_t)10 * cell;
+        for (int i = q; i < 10; i += 4) out[i] = k[i];
+    }
 }
 
 hipError_t launch_gram(const void *feat, int H, int W, int C, int dtype, double *gram, hipStream_t s)
 {
     const long cells = (long)H * W;
-    if (cells <= 0 || C % 4) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((cells + 255) / 256)), block(256);
+    if (cells <= 0 || C % 16) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((4 * cells + 255) / 256)), block(256);
     if (dtype == 0)
         hipLaunchKernelGGL(gram_kernel<0>, grid, block, 0, s, feat, H, W, C, gram);
     else

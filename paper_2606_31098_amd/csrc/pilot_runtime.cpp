@@ -331,6 +331,9 @@ void *stage_acquire(pilot_ctx *ctx, size_t bytes, int *which, int *rc)
 }
 
 // ---------------------------------------------------------------- tiles
+// pass variants 3 and 4 read per-cell Gram tables
+bool uses_gram(const TileConfig &tc) { return tc.variant == 3 || tc.variant == 4; }
+
 int log2_bucket(int n)
 {
     int b = 0;
@@ -531,7 +534,7 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
             g.passes = (only_level >= 0) ? 1 : 1 + iters;
             g.stat_class = class_index(l, g.C, g.dtype);
             g.tc.grid = grid_of(ctx, g.tc, g.n_items);
-            if (g.tc.variant == 3)
+            if (uses_gram(g.tc))
                 for (int i : kv.second) {
                     const pilot_level &Li = frames[i].level[l];
                     plan.gram_jobs.push_back(Plan::GramJob{i, l, plan.gram_bytes});
@@ -612,7 +615,7 @@ int ensure_state(pilot_ctx *ctx, Plan &plan)
 int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const LaunchGroup &g, int mode,
                  hipStream_t s, bool timed)
 {
-    if (g.tc.variant == 3)                     // every frame of the group needs its Gram table
+    if (uses_gram(g.tc))                       // every frame of the group needs its Gram table
         for (int t = g.tile_off; t < g.tile_off + g.n_tiles; ++t)
             if (!plan.frames[plan.tiles[t].frame].lv[g.level].gram)
                 return fail(ctx, PILOT_EDEVICE, "internal: pass variant 3 without a Gram table (level %d)", g.level);
@@ -700,7 +703,7 @@ void load_tune_cache(pilot_ctx *ctx)
     std::string key;
     TileConfig tc;
     while (in >> key >> tc.G >> tc.PPG >> tc.grid >> tc.variant)
-        if (pass_supported(16, 0, tc.G) && tc.PPG >= 1 && tc.PPG <= 64 && tc.variant >= 1 && tc.variant <= 3)
+        if (pass_supported(16, 0, tc.G) && tc.PPG >= 1 && tc.PPG <= 64 && tc.variant >= 1 && tc.variant <= 4)
             ctx->tuned[key] = tc;
 }
 
@@ -990,7 +993,7 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
     if ((rc = collect_timings(ctx))) return rc;           // earlier profiled launches go to the counters
 
     std::vector<TileConfig> cand;
-    for (int variant : {1, 2, 3})
+    for (int variant : {1, 2, 3, 4})
         for (int G : {4, 8, 16})
             for (int ppg : {2, 4, 8, 16})
                 for (int bpc : {0, 2, 4}) cand.push_back(TileConfig{G, ppg, bpc, variant});
@@ -1145,7 +1148,7 @@ size_t frame_cost(const pilot_ctx *ctx, const pilot_frame &f)
         if (L.qconf) in += (size_t)L.H * L.W * sizeof(float);
         if (L.ref_w) in += (size_t)L.N * sizeof(float);
         const TileConfig tc = choose_tile(ctx, L.C, L.dtype, L.N, f.M, (long)L.H * L.W);
-        if (tc.variant == 3) in += gram_table_bytes(L);
+        if (uses_gram(tc)) in += gram_table_bytes(L);
         const size_t items = (size_t)((f.M + tc.G - 1) / tc.G) * n_ptiles_of(tc, L.N);
         part = std::max(part, items * tc.G * kNV * sizeof(float));
     }
@@ -1321,7 +1324,7 @@ int pilot_admit(pilot_ctx *ctx, const pilot_frame *frame, const pilot_result *re
     bool gneed[PILOT_MAX_LEVELS] = {false};
     for (int l = 0; l < frame->n_levels; ++l) {
         const pilot_level &L = frame->level[l];
-        if (serving_tile(ctx, L.C, L.dtype, L.N, frame->M, (long)L.H * L.W).variant == 3) {
+        if (uses_gram(serving_tile(ctx, L.C, L.dtype, L.N, frame->M, (long)L.H * L.W))) {
             gneed[l] = true;
             goff[l] = gbytes;
             gbytes += gram_table_bytes(L);

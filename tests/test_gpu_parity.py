@@ -166,7 +166,7 @@ def _floor_log2(n):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
 @pytest.mark.parametrize("G", [4, 8, 16])
 def test_tile_shapes_and_kernel_variants_match_oracle(tmp_path, variant, G, dtype):
     """Every lane-group width and every pass-kernel variant (forced through a
