@@ -114,6 +114,7 @@ struct PassArgs {
     const PoseEval *pose;
     const int *hlev;             // level whose evaluation is pending; -1 finished
     float *partials;             // [item][G][kNV]
+    const int *run_flag;         // NULL, or 0 when no hypothesis is at this level (the launch has nothing to do)
 };
 
 struct EpilogueArgs {
@@ -128,6 +129,8 @@ struct EpilogueArgs {
     int *hlev;
     HypState *hs;
     unsigned long long *pairs;   // evaluated anchor x hypothesis pairs of this launch's class
+    const int *run_flag;         // as in PassArgs
+    int *next_flag;              // NULL, or set to 1 when a hypothesis stays at this level
 };
 
 }  // namespace pilot

@@ -30,6 +30,9 @@ hipError_t launch_init(const FrameDev *frames, int n_frames, int max_M, HypState
                        PoseEval *pose, int *hlev, int mode, const double *diag_poses,
                        int diag_level, hipStream_t s);
 
+// Pass flags of a solve (see EpilogueArgs::next_flag): n flags, stride per level.
+hipError_t launch_reset_flags(int *flags, int n, int stride, hipStream_t s);
+
 // Per-cell Gram matrices of the bilinear coefficients of a feature map
 // (pass kernel variant 3): 10 doubles per cell, cells y0 W + x0.
 hipError_t launch_gram(const void *feat, int H, int W, int C, int dtype, double *gram, hipStream_t s);

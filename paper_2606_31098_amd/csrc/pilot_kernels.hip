@@ -44,6 +44,7 @@ __global__ __launch_bounds__(kEpiThreads) void epilogue_kernel(EpilogueArgs e)
     __shared__ double s_part[kEpiThreads];
     __shared__ HypState s_hs[kMaxG];
     __shared__ PoseEval s_pe[kMaxG];
+    if (e.run_flag && *e.run_flag == 0) return;   // no hypothesis left at this level
     const TileItem ti = e.tiles[blockIdx.x];
     const FrameDev *f = e.frames + ti.frame;
     const int G = e.G;
@@ -136,7 +137,21 @@ __global__ __launch_bounds__(kEpiThreads) void epilogue_kernel(EpilogueArgs e)
         e.hs[gh] = s;
         e.pose[gh] = p;
         e.hlev[gh] = hl;
+        if (e.next_flag && hl == e.level) *e.next_flag = 1;   // the next pass of this level has work
     }
+}
+
+// Pass flags of a solve: flag (l, 0) = 1 (every level's first pass runs),
+// the others 0 until an epilogue raises them.
+__global__ void reset_flags_kernel(int *flags, int n, int stride)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) flags[i] = (i % stride == 0) ? 1 : 0;
+}
+
+hipError_t launch_reset_flags(int *flags, int n, int stride, hipStream_t s)
+{
+    hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(256), 0, s, flags, n, stride);
+    return hipGetLastError();
 }
 
 hipError_t launch_epilogue(const EpilogueArgs &e, hipStream_t s)

@@ -69,6 +69,7 @@ struct Plan {
     };
     std::vector<GramJob> gram_jobs;
     size_t gram_bytes = 0;
+    int flag_stride = 1;         // pass flags per level (most passes of a level's groups + 1)
 };
 
 struct TimedLaunch {
@@ -103,7 +104,7 @@ struct pilot_ctx {
     std::string err;
 
     // workspace
-    DevBuf desc, hs, pose, hlev, partials, pairs, gram;
+    DevBuf desc, hs, pose, hlev, partials, pairs, gram, passflag;
     size_t ws_bytes = 0;
     unsigned generation = 0;
 
@@ -532,6 +533,7 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
             g.n_items = (int)plan.items.size() - g.item_off;
             g.n_tiles = (int)plan.tiles.size() - g.tile_off;
             g.passes = (only_level >= 0) ? 1 : 1 + iters;
+            plan.flag_stride = std::max(plan.flag_stride, g.passes + 1);
             g.stat_class = class_index(l, g.C, g.dtype);
             g.tc.grid = grid_of(ctx, g.tc, g.n_items);
             if (uses_gram(g.tc))
@@ -608,12 +610,13 @@ int ensure_state(pilot_ctx *ctx, Plan &plan)
     if ((rc = ensure(ctx, ctx->hlev, H * sizeof(int)))) return rc;
     if ((rc = ensure(ctx, ctx->partials, std::max<size_t>(1, plan.partial_floats) * sizeof(float)))) return rc;
     if ((rc = ensure(ctx, ctx->pairs, kStatClasses * sizeof(unsigned long long), true))) return rc;
+    if ((rc = ensure(ctx, ctx->passflag, (size_t)PILOT_MAX_LEVELS * plan.flag_stride * sizeof(int)))) return rc;
     return PILOT_OK;
 }
 
 // Enqueue one pass (pass kernel + epilogue) of a launch group.
 int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const LaunchGroup &g, int mode,
-                 hipStream_t s, bool timed)
+                 hipStream_t s, bool timed, const int *run_flag = nullptr, int *next_flag = nullptr)
 {
     if (uses_gram(g.tc))                       // every frame of the group needs its Gram table
         for (int t = g.tile_off; t < g.tile_off + g.n_tiles; ++t)
@@ -627,6 +630,7 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Laun
     a.pose = (const PoseEval *)ctx->pose.p;
     a.hlev = (const int *)ctx->hlev.p;
     a.partials = (float *)ctx->partials.p;
+    a.run_flag = run_flag;
     TimedLaunch tl{};
     if (timed) {
         tl.a = pool_event(ctx);
@@ -653,6 +657,8 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Laun
     e.hlev = (int *)ctx->hlev.p;
     e.hs = (HypState *)ctx->hs.p;
     e.pairs = (unsigned long long *)ctx->pairs.p + g.stat_class;
+    e.run_flag = run_flag;
+    e.next_flag = next_flag;
     HIPCHK(ctx, launch_epilogue(e, s));
     ctx->launches[g.stat_class]++;
     return PILOT_OK;
@@ -673,6 +679,7 @@ int enqueue_gram(pilot_ctx *ctx, const Plan &plan, hipStream_t s)
 int enqueue_schedule(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, hipStream_t s, bool timed)
 {
     if (int rc = enqueue_gram(ctx, plan, s)) return rc;
+    HIPCHK(ctx, launch_reset_flags((int *)ctx->passflag.p, PILOT_MAX_LEVELS * plan.flag_stride, plan.flag_stride, s));
     HIPCHK(ctx, launch_init(dp.frames, (int)plan.frames.size(), plan.max_M, (HypState *)ctx->hs.p,
                             (PoseEval *)ctx->pose.p, (int *)ctx->hlev.p, MODE_LM, nullptr, 0, s));
     for (int l = 0; l < plan.max_levels; ++l) {
@@ -682,7 +689,9 @@ int enqueue_schedule(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, hipStr
         for (int k = 0; k < maxp; ++k)
             for (const LaunchGroup &g : plan.groups)
                 if (g.level == l && k < g.passes) {
-                    int rc = enqueue_pass(ctx, plan, dp, g, MODE_LM, s, timed);
+                    // pass k of level l runs only if pass k - 1 left a hypothesis at level l
+                    int *flags = (int *)ctx->passflag.p + (size_t)l * plan.flag_stride;
+                    int rc = enqueue_pass(ctx, plan, dp, g, MODE_LM, s, timed, flags + k, flags + k + 1);
                     if (rc) return rc;
                 }
         bool prunes = false;
