@@ -332,8 +332,8 @@ void *stage_acquire(pilot_ctx *ctx, size_t bytes, int *which, int *rc)
 }
 
 // ---------------------------------------------------------------- tiles
-// pass variants 3 and 4 read per-cell Gram tables
-bool uses_gram(const TileConfig &tc) { return tc.variant == 3 || tc.variant == 4; }
+// pass variants 3 to 6 read per-cell Gram tables
+bool uses_gram(const TileConfig &tc) { return tc.variant >= 3 && tc.variant <= 6; }
 
 int log2_bucket(int n)
 {
@@ -712,7 +712,7 @@ void load_tune_cache(pilot_ctx *ctx)
     std::string key;
     TileConfig tc;
     while (in >> key >> tc.G >> tc.PPG >> tc.grid >> tc.variant)
-        if (pass_supported(16, 0, tc.G) && tc.PPG >= 1 && tc.PPG <= 64 && tc.variant >= 1 && tc.variant <= 4)
+        if (pass_supported(16, 0, tc.G) && tc.PPG >= 1 && tc.PPG <= 64 && tc.variant >= 1 && tc.variant <= 6)
             ctx->tuned[key] = tc;
 }
 
@@ -1002,10 +1002,15 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
     if ((rc = collect_timings(ctx))) return rc;           // earlier profiled launches go to the counters
 
     std::vector<TileConfig> cand;
-    for (int variant : {1, 2, 3, 4})
+    // variants 5 and 6 differ from 3 and 4 for bf16 maps only
+    bool bf16 = false;
+    for (int l = 0; l < frame->n_levels; ++l) bf16 = bf16 || frame->level[l].dtype == PILOT_BF16;
+    for (int variant : {1, 2, 3, 4, 5, 6}) {
+        if (variant >= 5 && !bf16) continue;
         for (int G : {4, 8, 16})
             for (int ppg : {2, 4, 8, 16})
                 for (int bpc : {0, 2, 4}) cand.push_back(TileConfig{G, ppg, bpc, variant});
+    }
 
     // scratch outputs of the timed solves
     const int M = frame->M;

@@ -166,14 +166,20 @@ def _floor_log2(n):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("G", [4, 8, 16])
 def test_tile_shapes_and_kernel_variants_match_oracle(tmp_path, variant, G, dtype):
     """Every lane-group width and every pass-kernel variant (forced through a
     tune cache) reproduces the oracle's normal equations and solves (bf16: the
-    oracle runs on the same rounded maps and descriptors)."""
+    oracle runs on the same rounded maps and descriptors).  Variant 5 with bf16
+    maps (and 6, the same at three waves per SIMD) sums the tap dot products in
+    FP32 (the precision form): its bar is the bf16 one, with the normal
+    equations to 1e-4 and the cost to 1e-5."""
     from paper_2606_31098_amd.pilot import Context, DeviceFrame
     d = 0 if dtype == "f32" else 1
+    fp32_dots = variant in (5, 6) and dtype == "bf16"
+    neq_tol, cost_tol = (1e-4, 1e-5) if fp32_dots else (NEQ_TOL, 1e-9)
+    tol_m, tol_deg = (BF16_TOL_M, BF16_TOL_DEG) if fp32_dots else (POSE_TOL_M, POSE_TOL_DEG)
 
     def frame():
         fr = pyramid_frame(seed=8, N=900, M=11, iters=(4, 4, 4))
@@ -204,11 +210,11 @@ def test_tile_shapes_and_kernel_variants_match_oracle(tmp_path, variant, G, dtyp
         for m in range(f.M):
             Ho, go, co, no = oracle.linearize(of, lvl, poses[m])
             err = rel_frobenius(np.concatenate([H[m], g[m][:, None]], 1), np.concatenate([Ho, go[:, None]], 1))
-            assert err <= NEQ_TOL, (lvl, m, err)
-            assert abs(cost[m] - co) <= 1e-9 * abs(co), (lvl, m)
+            assert err <= neq_tol, (lvl, m, err)
+            assert abs(cost[m] - co) <= cost_tol * abs(co), (lvl, m, (cost[m] - co) / co)
     gpu = c.solve([DeviceFrame(f, dtype=dtype)])[0].numpy()
     orc = oracle.solve(f, threads=8)
-    rows, fails = compare_solutions(f, gpu, orc, POSE_TOL_M, POSE_TOL_DEG, f"v{variant}G{G}{dtype}")
+    rows, fails = compare_solutions(f, gpu, orc, tol_m, tol_deg, f"v{variant}G{G}{dtype}")
     assert not fails, fails
 
 
