@@ -41,7 +41,7 @@ constexpr int kEpiThreads = 512;
 __global__ __launch_bounds__(kEpiThreads) void epilogue_kernel(EpilogueArgs e)
 {
     __shared__ double s_sum[kMaxG][kNV];
-    __shared__ double s_part[kEpiThreads];
+    __shared__ double s_part[4 * kEpiThreads];     // R x G x kNV partial sums
     __shared__ HypState s_hs[kMaxG];
     __shared__ PoseEval s_pe[kMaxG];
     if (e.run_flag && *e.run_flag == 0) return;   // no hypothesis left at this level
@@ -54,57 +54,63 @@ __global__ __launch_bounds__(kEpiThreads) void epilogue_kernel(EpilogueArgs e)
     unsigned act = 0;
     for (int hh = 0; hh < nh; ++hh) act |= (e.hlev[hb + hh] == e.level ? 1u : 0u) << hh;
     if (act == 0) return;
-    // R threads per value: thread (r, t) sums the items r, r + R, r + 2R, ...
-    // of value t (eight interleaved accumulators, so eight loads are in
-    // flight), then the R partial sums are added in r order: a fixed order
-    // for a given tile shape
+    // The tile's records are read as float4 columns (4 adjacent values; a
+    // hypothesis' 32 slots are 8 columns, the last holding the FP64 cost bits).
+    // R threads per column: thread (r, q) sums the items r, r + R, r + 2R, ...
+    // of column q, issuing the loads of 8 items before adding them in item
+    // order; then the R partial sums are added in r order.  The order depends
+    // on the tile shape only.
     const int stride = G * kNV;
-    const int R = kEpiThreads / stride;
-    const int tv = threadIdx.x % stride, r = threadIdx.x / stride;
+    const int Q = stride / 4;
+    const int R = kEpiThreads / Q;
+    const int q = threadIdx.x % Q, r = threadIdx.x / Q;
     {
-        const int v = tv % kNV;
-        const float *src = e.partials + (size_t)ti.first_item * stride + tv;
+        const bool cost_col = (q % (kNV / 4)) == kCostSlot / 4;
+        const float4 *src = reinterpret_cast<const float4 *>(e.partials + (size_t)ti.first_item * stride) + q;
         const int n = ti.n_ptiles;
-        double a[8];
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int it = r;
+        for (; it + 7 * R < n; it += 8 * R) {
+            float4 x[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) a[k] = 0.0;
-        if (r < R) {
-            if (v < kNSum) {
-                int it = r;
-                for (; it + 7 * R < n; it += 8 * R) {
-                    float x[8];
+            for (int k = 0; k < 8; ++k) x[k] = src[(size_t)(it + k * R) * Q];
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) x[k] = src[(size_t)(it + k * R) * stride];
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) a[k] += (double)x[k];
+            for (int k = 0; k < 8; ++k) {
+                if (cost_col) {
+                    a0 += __longlong_as_double((long long)((unsigned long long)__float_as_uint(x[k].x) |
+                                                           ((unsigned long long)__float_as_uint(x[k].y) << 32)));
+                } else {
+                    a0 += (double)x[k].x;
+                    a1 += (double)x[k].y;
+                    a2 += (double)x[k].z;
+                    a3 += (double)x[k].w;
                 }
-                for (; it < n; it += R) a[0] += (double)src[(size_t)it * stride];
-            } else if (v == kCostSlot) {
-                auto cost_at = [&](int i) {
-                    const float *q = src + (size_t)i * stride;
-                    const unsigned long long bits = (unsigned long long)__float_as_uint(q[0]) |
-                                                    ((unsigned long long)__float_as_uint(q[1]) << 32);
-                    return __longlong_as_double((long long)bits);
-                };
-                int it = r;
-                for (; it + 7 * R < n; it += 8 * R) {
-                    double x[8];
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) x[k] = cost_at(it + k * R);
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) a[k] += x[k];
-                }
-                for (; it < n; it += R) a[0] += cost_at(it);
             }
-            s_part[r * stride + tv] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         }
+        for (; it < n; it += R) {
+            const float4 x = src[(size_t)it * Q];
+            if (cost_col) {
+                a0 += __longlong_as_double((long long)((unsigned long long)__float_as_uint(x.x) |
+                                                       ((unsigned long long)__float_as_uint(x.y) << 32)));
+            } else {
+                a0 += (double)x.x;
+                a1 += (double)x.y;
+                a2 += (double)x.z;
+                a3 += (double)x.w;
+            }
+        }
+        double *dst = s_part + (size_t)r * stride + 4 * q;
+        dst[0] = a0;
+        dst[1] = cost_col ? 0.0 : a1;
+        dst[2] = cost_col ? 0.0 : a2;
+        dst[3] = cost_col ? 0.0 : a3;
     }
     __syncthreads();
-    if (threadIdx.x < stride) {
+    for (int tv = threadIdx.x; tv < stride; tv += kEpiThreads) {
         const int hh = tv / kNV, v = tv - hh * kNV;
-        double s = 0.0;
-        for (int q = 0; q < R; ++q) s += s_part[q * stride + tv];
-        s_sum[hh][v] = s;
+        double sum = 0.0;
+        for (int k = 0; k < R; ++k) sum += s_part[(size_t)k * stride + tv];
+        s_sum[hh][v] = sum;
     }
     __syncthreads();
     if (threadIdx.x == 0)
