@@ -36,8 +36,11 @@
  *              (lambda /= down, floor lambda_min_rel max diag H), otherwise
  *              rejected (lambda *= up; reaching lambda_max_rel max diag H
  *              stops the level, STALLED); an accepted step with
- *              |d rho| < step_tol_t and |d omega| < step_tol_r ends the level
- *              (CONVERGED); every iteration, accepted or not, counts.
+ *              |d rho| < step_tol_t and |d omega| < step_tol_r, or a
+ *              candidate whose cost is within cost_tol * cost of the current
+ *              one, ends the level (CONVERGED); every iteration, accepted or
+ *              not, counts.  The prior scales are lambda_imu, lambda_range, or
+ *              (adaptive_priors) set at each level's start and held for it.
  *   selection  best = lowest final cost among hypotheses that are neither
  *              degenerate nor pruned, ties to the lowest index, -1 if none.
  *
@@ -277,9 +280,14 @@ int pilot_serving_state(pilot_ctx *ctx, int *active_slots, size_t *bytes_in_use)
 /* Counters since creation (or the last reset). */
 int pilot_get_stats(pilot_ctx *ctx, pilot_stats *out, int reset);
 
-/* Autotune the pass kernel for the shapes of `frame` now (times candidate
- * tile configurations with hipEvents on the stream); the choice is cached
- * per shape class and appended to the tune cache file. */
+/* Autotune the pass kernel for the level shapes of `frame` now: every
+ * candidate tile (kernel variant, lane-group width, anchors per lane group,
+ * grid) is timed by eager solves of `frame` with hipEvents around each pass,
+ * and each level shape (C, dtype, log2 N, log2 M, log2 H*W) keeps the
+ * candidate with the lowest summed pass time; the choice is cached in the
+ * context and appended to the tune cache file.  Synchronises the stream;
+ * leaves the counters of pilot_get_stats as they were.  Shapes already
+ * tuned are skipped. */
 int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame);
 
 /* "G=8 PPG=8 BPC=2 V=3 tuned=1" style description of the tile choice for a
