@@ -505,8 +505,8 @@ def run_serving_config(args, worlds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding of frames "
-                                   "and hypotheses is a design note, not part of this build)"}))
+        print(json.dumps({"error": "--gpus must be 1: the solver runs on one GPU (frames and hypothesis ranges "
+                                   "would shard across GPUs with one all-gather of costs; not implemented)"}))
         sys.exit(2)
     if args.calibrate_copy:
         import torch

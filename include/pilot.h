@@ -68,7 +68,7 @@ enum {
     PILOT_ENOMEM = -2,        /* workspace would exceed the HBM budget       */
     PILOT_EDEVICE = -3,       /* HIP runtime failure; message carries it     */
     PILOT_EAGAIN = -4,        /* serving: no slot or budget free right now   */
-    PILOT_EUNSUPPORTED = -5   /* valid request this build does not handle    */
+    PILOT_EUNSUPPORTED = -5   /* valid request the library does not handle   */
 };
 
 enum { PILOT_F32 = 0, PILOT_BF16 = 1 };

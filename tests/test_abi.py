@@ -86,3 +86,14 @@ def test_product_path_has_no_oracle_dependency():
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt and "liboracle" not in txt, fn
                 assert "oracle.h" not in txt, fn
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N with N > 1 exits with a message (one GPU here)."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "--gpus must be 1" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
