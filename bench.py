@@ -33,6 +33,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# wave-level VALU instructions the chip can issue per cycle: 256 CUs x 4 SIMDs,
+# one wave64 instruction per SIMD every 4 cycles (16 lanes per cycle)
+VALU_ISSUE_PER_CYCLE = 256 * 4 / 4
 METRIC = "point-residual evals/s (GB/s vs HBM peak); p50/p99 frame latency, BF16 vs FP32"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_kernel_traffic.json")
 TILES_FILE = os.path.join(ROOT, "paper_2606_31098_amd", "tiles_gfx950.txt")
@@ -138,15 +141,24 @@ def roofline_leg(args, dfs, steps):
     avg_ms = pst.pass_ms[fine] / n_launch
     bytes_per_launch = pst.pair_bytes[fine] / n_launch
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = None
+    traffic, counters = None, None
     if os.path.exists(TRAFFIC_FILE):
         try:
             tj = json.load(open(TRAFFIC_FILE))
             entry = tj.get(f"config{args.config}")
             if entry and entry.get("pass_kernel_digest") == B.pass_kernel_digest():
                 traffic = entry.get("bytes_per_launch")
+                # what the counters say bounds the kernel: VALU issue rate and fabric traffic
+                cyc = entry.get("gpu_cycles_per_launch")
+                valu = entry.get("valu_instructions_per_launch")
+                if cyc and valu:
+                    counters = {"valu_issue_frac": round(valu / (VALU_ISSUE_PER_CYCLE * cyc), 3),
+                                "fabric_GBps": round(traffic / (avg_ms * 1e-3) / 1e9, 1),
+                                "fabric_frac_of_hbm": round(traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
+                                "l2_hit_rate": entry.get("l2_hit_rate"),
+                                "source": "profiles/pass_kernel_traffic.json (rocprofv3 --pmc, same kernel sources)"}
         except (OSError, ValueError):
-            traffic = None
+            traffic, counters = None, None
     C = dfs[0].s.level[fine].C
     dt = "bf16" if dfs[0].s.level[fine].dtype == A.BF16 else "f32"
     pctx.close()
@@ -155,7 +167,7 @@ def roofline_leg(args, dfs, steps):
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": f"pass_kernel<{C}, {dt}> (level {fine})", "launches": int(n_launch),
             "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": int(bytes_per_launch),
-            "pairs_per_launch": int(pst.pairs[fine] / n_launch),
+            "pairs_per_launch": int(pst.pairs[fine] / n_launch), "counters": counters,
             "profiled_ms_per_step": round(pwall * 1e3 / steps, 3)}
 
 
