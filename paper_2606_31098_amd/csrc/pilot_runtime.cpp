@@ -203,14 +203,16 @@ int validate_frame(pilot_ctx *ctx, const pilot_frame *f, int fi, bool need_poses
                 return fail(ctx, PILOT_EUNSUPPORTED, "frames[%d].level[%d].C: %d channels has no kernel (16, 32, 64, 128, 256)", fi, l, L.C);
             return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].C: must be 16, 32, 64, 128 or 256 (got %d)", fi, l, L.C);
         }
-        if ((double)L.H * L.W * L.C >= 2147483647.0)
-            return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d]: H*W*C must be < 2^31", fi, l);
+        // the kernels address maps, descriptors and per-cell tables with 32-bit byte offsets
+        if ((double)L.H * L.W * L.C * elem_size(L.dtype) >= 4294967296.0 || (double)L.H * L.W * 80.0 >= 4294967296.0)
+            return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d]: the map (H*W*C elements) must be under 4 GiB", fi, l);
         if (!L.feat) return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].feat: NULL", fi, l);
         if (!aligned16(L.feat)) return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].feat: must be 16-byte aligned", fi, l);
         if (!finite_all(L.K, 4) || !(L.K[0] > 0) || !(L.K[1] > 0))
             return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].K: fx, fy must be > 0 and all finite", fi, l);
-        if (L.N < 0 || (double)L.N * L.C >= 2147483647.0)
-            return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].N: must be >= 0 with N*C < 2^31 (got %d)", fi, l, L.N);
+        if (L.N < 0 || (double)L.N * L.C * elem_size(L.dtype) >= 4294967296.0)
+            return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].N: must be >= 0 with N*C elements under 4 GiB (got %d)",
+                        fi, l, L.N);
         if (L.N > 0) {
             if (!L.x || !L.y || !L.z) return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].x/y/z: NULL", fi, l);
             if (!L.ref) return fail(ctx, PILOT_EINVAL, "frames[%d].level[%d].ref: NULL", fi, l);
