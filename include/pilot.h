@@ -95,7 +95,10 @@ typedef struct {
     int32_t reserved;
 } pilot_config;
 
-/* One pyramid level (Eq. (1) at level l, scaled intrinsics K_l). */
+/* One pyramid level (Eq. (1) at level l, scaled intrinsics K_l).  The kernels
+ * address each level's arrays with 32-bit byte offsets: the map (H*W*C
+ * elements), the descriptors (N*C elements) and the per-cell table the library
+ * builds (80*H*W bytes) must each be under 4 GiB, else PILOT_EINVAL. */
 typedef struct {
     int32_t H, W, C;            /* C in {16, 32, 64, 128, 256}; H, W >= 2             */
     int32_t dtype;              /* PILOT_F32 or PILOT_BF16, for feat and ref         */

@@ -207,6 +207,15 @@ def test_abi_errors_launch_nothing(alone):
     bad = A.Frame.from_buffer_copy(base)
     bad.adaptive_priors, bad.alpha_ratio = 1, float("nan")
     expect(A.EINVAL, bad, "alpha_ratio")
+    # 32-bit byte offsets: a map or a descriptor set of 4 GiB or more is refused
+    # before anything is read
+    bad = A.Frame.from_buffer_copy(base)
+    bad.level[0].H, bad.level[0].W = 8192, 8192
+    assert 8192 * 8192 * bad.level[0].C * 4 >= 1 << 32 and bad.level[0].dtype == A.F32
+    expect(A.EINVAL, bad, "level[0]: the map")
+    bad = A.Frame.from_buffer_copy(base)
+    bad.level[0].N = 1 << 27
+    expect(A.EINVAL, bad, "level[0].N")
     bad = A.Frame.from_buffer_copy(base)
     bad.level[2].loss_scale = float("nan")
     expect(A.EINVAL, bad, "loss_scale")
