@@ -62,7 +62,7 @@ struct Plan {
     int total_hyps = 0, max_M = 0, max_levels = 0;
     size_t partial_floats = 0;
     std::string key;
-    // Gram tables of the (frame, level) pairs whose tiles use pass variant 3
+    // Gram tables of the (frame, level) pairs whose tiles use a Gram pass variant (3 to 8)
     struct GramJob {
         int frame, level;
         size_t offset;
@@ -85,7 +85,7 @@ struct ServingSlot {
     uint64_t admit_step = 0;
     pilot_frame frame;
     FrameDev dev{};      // host copy of the slot's device descriptor
-    DevBuf gram;         // Gram tables of the slot's variant-3 levels (kept for reuse)
+    DevBuf gram;         // Gram tables of the slot's Gram-variant levels (kept for reuse)
 };
 
 constexpr int kFlagRing = 4;
@@ -334,8 +334,8 @@ void *stage_acquire(pilot_ctx *ctx, size_t bytes, int *which, int *rc)
 }
 
 // ---------------------------------------------------------------- tiles
-// pass variants 3 to 6 read per-cell Gram tables
-bool uses_gram(const TileConfig &tc) { return tc.variant >= 3 && tc.variant <= 6; }
+// pass variants 3 to 8 read per-cell Gram tables
+bool uses_gram(const TileConfig &tc) { return tc.variant >= 3 && tc.variant <= 8; }
 
 int log2_bucket(int n)
 {
@@ -623,7 +623,7 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Laun
     if (uses_gram(g.tc))                       // every frame of the group needs its Gram table
         for (int t = g.tile_off; t < g.tile_off + g.n_tiles; ++t)
             if (!plan.frames[plan.tiles[t].frame].lv[g.level].gram)
-                return fail(ctx, PILOT_EDEVICE, "internal: pass variant 3 without a Gram table (level %d)", g.level);
+                return fail(ctx, PILOT_EDEVICE, "internal: Gram pass variant without a Gram table (level %d)", g.level);
     PassArgs a;
     a.frames = dp.frames;
     a.items = dp.items + g.item_off;
@@ -666,7 +666,7 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Laun
     return PILOT_OK;
 }
 
-// Gram tables of the plan's variant-3 levels (they depend on the feature
+// Gram tables of the plan's Gram-variant levels (they depend on the feature
 // maps only, and are rebuilt with every solve since a replay may see new maps).
 int enqueue_gram(pilot_ctx *ctx, const Plan &plan, hipStream_t s)
 {
@@ -714,7 +714,7 @@ void load_tune_cache(pilot_ctx *ctx)
     std::string key;
     TileConfig tc;
     while (in >> key >> tc.G >> tc.PPG >> tc.grid >> tc.variant)
-        if (pass_supported(16, 0, tc.G) && tc.PPG >= 1 && tc.PPG <= 64 && tc.variant >= 1 && tc.variant <= 6)
+        if (pass_supported(16, 0, tc.G) && tc.PPG >= 1 && tc.PPG <= 64 && tc.variant >= 1 && tc.variant <= 8)
             ctx->tuned[key] = tc;
 }
 
@@ -1004,11 +1004,11 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
     if ((rc = collect_timings(ctx))) return rc;           // earlier profiled launches go to the counters
 
     std::vector<TileConfig> cand;
-    // variants 5 and 6 differ from 3 and 4 for bf16 maps only
+    // variants 5, 6 and 8 differ from 3, 4 and 7 for bf16 maps only
     bool bf16 = false;
     for (int l = 0; l < frame->n_levels; ++l) bf16 = bf16 || frame->level[l].dtype == PILOT_BF16;
-    for (int variant : {1, 2, 3, 4, 5, 6}) {
-        if (variant >= 5 && !bf16) continue;
+    for (int variant : {1, 2, 3, 4, 5, 6, 7, 8}) {
+        if ((variant == 5 || variant == 6 || variant == 8) && !bf16) continue;
         for (int G : {4, 8, 16})
             for (int ppg : {2, 4, 8, 16})
                 for (int bpc : {0, 2, 4}) cand.push_back(TileConfig{G, ppg, bpc, variant});
@@ -1334,7 +1334,7 @@ int pilot_admit(pilot_ctx *ctx, const pilot_frame *frame, const pilot_result *re
     fill_frame_dev(d, *frame, result, base);
     d.slot = s;
     d.done_flag = (int *)ctx->s_done.p + s;
-    // Gram tables of the levels whose tiles use pass variant 3, in the slot's own buffer
+    // Gram tables of the levels whose tiles use a Gram variant, in the slot's own buffer
     ServingSlot &sl = ctx->slots[s];
     size_t gbytes = 0, goff[PILOT_MAX_LEVELS] = {0};
     bool gneed[PILOT_MAX_LEVELS] = {false};

@@ -166,18 +166,19 @@ def _floor_log2(n):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("G", [4, 8, 16])
 def test_tile_shapes_and_kernel_variants_match_oracle(tmp_path, variant, G, dtype):
     """Every lane-group width and every pass-kernel variant (forced through a
     tune cache) reproduces the oracle's normal equations and solves (bf16: the
     oracle runs on the same rounded maps and descriptors).  Variant 5 with bf16
-    maps (and 6, the same at three waves per SIMD) sums the tap dot products in
-    FP32 (the precision form): its bar is the bf16 one, with the normal
-    equations to 1e-4 and the cost to 1e-5."""
+    maps (and 6, the same at three waves per SIMD, and 8, the same with the tap
+    sums transposed through LDS) sums the tap dot products in FP32 (the
+    precision form): its bar is the bf16 one, with the normal equations to 1e-4
+    and the cost to 1e-5.  Variant 7 is variant 3 with the LDS transpose."""
     from paper_2606_31098_amd.pilot import Context, DeviceFrame
     d = 0 if dtype == "f32" else 1
-    fp32_dots = variant in (5, 6) and dtype == "bf16"
+    fp32_dots = variant in (5, 6, 8) and dtype == "bf16"
     neq_tol, cost_tol = (1e-4, 1e-5) if fp32_dots else (NEQ_TOL, 1e-9)
     tol_m, tol_deg = (BF16_TOL_M, BF16_TOL_DEG) if fp32_dots else (POSE_TOL_M, POSE_TOL_DEG)
 
