@@ -69,9 +69,9 @@ struct FrameDev {
 // A tile of G hypotheses x P anchors of one frame at one level.
 struct WorkItem {
     int frame;       // index into the FrameDev table
-    int htile;       // hypothesis tile (G hypotheses)
+    int hbase;       // global index of the tile's first hypothesis (frame base + tile * G)
     int ptile;       // anchor tile (P anchors)
-    int pad;
+    int nh;          // hypotheses in the tile (G, fewer in a frame's last tile)
 };
 
 // A hypothesis tile of one frame and the run of work items holding its partials.
@@ -80,6 +80,8 @@ struct TileItem {
     int htile;
     int first_item;  // item index of anchor tile 0
     int n_ptiles;
+    int hbase;       // global index of the tile's first hypothesis
+    int nh;          // hypotheses in the tile
 };
 
 // LM state of one hypothesis (FP64 master pose and damped system).
@@ -129,7 +131,6 @@ struct EpilogueArgs {
     int *hlev;
     HypState *hs;
     unsigned long long *pairs;   // evaluated anchor x hypothesis pairs of this launch's class
-    const int *run_flag;         // as in PassArgs
     int *next_flag;              // NULL, or set to 1 when a hypothesis stays at this level
 };
 

@@ -44,15 +44,18 @@ __global__ __launch_bounds__(kEpiThreads) void epilogue_kernel(EpilogueArgs e)
     __shared__ double s_part[4 * kEpiThreads];     // R x G x kNV partial sums
     __shared__ HypState s_hs[kMaxG];
     __shared__ PoseEval s_pe[kMaxG];
-    if (e.run_flag && *e.run_flag == 0) return;   // no hypothesis left at this level
+    // one block per tile: the tile's own mask (lane hh < nh of each wave reads
+    // the level of hypothesis hb + hh, one load round trip) also covers a
+    // level with no hypothesis left, so the run flag is not read here
     const TileItem ti = e.tiles[blockIdx.x];
     const FrameDev *f = e.frames + ti.frame;
     const int G = e.G;
     const int h0 = ti.htile * G;
-    const int hb = f->hyp_base + h0;
-    const int nh = min(G, f->M - h0);
-    unsigned act = 0;
-    for (int hh = 0; hh < nh; ++hh) act |= (e.hlev[hb + hh] == e.level ? 1u : 0u) << hh;
+    const int hb = ti.hbase;
+    const int nh = ti.nh;
+    const int lane = threadIdx.x & 63;
+    const int lv = lane < nh ? e.hlev[hb + lane] : -1;
+    const unsigned act = __builtin_amdgcn_readfirstlane((unsigned)__ballot(lv == e.level));
     if (act == 0) return;
     // The tile's records are read as float4 columns (4 adjacent values; a
     // hypothesis' 32 slots are 8 columns, the last holding the FP64 cost bits).

@@ -527,9 +527,11 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
                 const int nht = (frames[i].M + g.tc.G - 1) / g.tc.G;
                 const int npt = n_ptiles_of(g.tc, frames[i].level[l].N);
                 for (int ht = 0; ht < nht; ++ht) {
-                    TileItem ti{i, ht, (int)plan.items.size() - g.item_off, npt};
-                    plan.tiles.push_back(ti);
-                    for (int pt = 0; pt < npt; ++pt) plan.items.push_back(WorkItem{i, ht, pt, 0});
+                    const int h0 = ht * g.tc.G, nh = std::min(g.tc.G, frames[i].M - h0);
+                    plan.tiles.push_back(
+                        TileItem{i, ht, (int)plan.items.size() - g.item_off, npt, plan.frames[i].hyp_base + h0, nh});
+                    for (int pt = 0; pt < npt; ++pt)
+                        plan.items.push_back(WorkItem{i, plan.frames[i].hyp_base + h0, pt, nh});
                 }
             }
             g.n_items = (int)plan.items.size() - g.item_off;
@@ -659,7 +661,6 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Laun
     e.hlev = (int *)ctx->hlev.p;
     e.hs = (HypState *)ctx->hs.p;
     e.pairs = (unsigned long long *)ctx->pairs.p + g.stat_class;
-    e.run_flag = run_flag;
     e.next_flag = next_flag;
     HIPCHK(ctx, launch_epilogue(e, s));
     ctx->launches[g.stat_class]++;
@@ -1261,8 +1262,11 @@ int serving_rebuild(pilot_ctx *ctx)
                 const int nht = (frames[k].M + g.tc.G - 1) / g.tc.G;
                 const int npt = n_ptiles_of(g.tc, frames[k].level[l].N);
                 for (int ht = 0; ht < nht; ++ht) {
-                    plan.tiles.push_back(TileItem{slot, ht, (int)plan.items.size() - g.item_off, npt});
-                    for (int pt = 0; pt < npt; ++pt) plan.items.push_back(WorkItem{slot, ht, pt, 0});
+                    const int h0 = ht * g.tc.G, nh = std::min(g.tc.G, frames[k].M - h0);
+                    plan.tiles.push_back(TileItem{slot, ht, (int)plan.items.size() - g.item_off, npt,
+                                                  ctx->slots[slot].hyp_base + h0, nh});
+                    for (int pt = 0; pt < npt; ++pt)
+                        plan.items.push_back(WorkItem{slot, ctx->slots[slot].hyp_base + h0, pt, nh});
                 }
             }
             g.n_items = (int)plan.items.size() - g.item_off;

@@ -321,7 +321,7 @@ def test_autotune_writes_every_level_key_and_stays_correct(tmp_path):
     assert {ln[0] for ln in lines} == keys and len(lines) == len(keys)
     for ln in lines:
         G, ppg, bpc, var = map(int, ln[1:])
-        assert G in (4, 8, 16) and ppg in (2, 4, 8, 16) and bpc in (0, 2, 4) and var in (1, 2, 3, 4, 5, 6)
+        assert G in (4, 8, 16) and ppg in (2, 4, 8, 16) and bpc in (0, 2, 4) and var in (1, 2, 3, 4, 5, 6, 7, 8)
     ctx2 = Context(0, tune_cache=str(cache))
     for L in f.levels:
         assert "tuned=1" in ctx2.tile_choice(L.C, 0, L.N, f.M, L.H * L.W)
