@@ -57,6 +57,22 @@ __global__ __launch_bounds__(kEpiThreads) void epilogue_kernel(EpilogueArgs e)
     const int lv = lane < nh ? e.hlev[hb + lane] : -1;
     const unsigned act = __builtin_amdgcn_readfirstlane((unsigned)__ballot(lv == e.level));
     if (act == 0) return;
+    // LM states and poses of the tile's hypotheses, fetched by the whole block
+    // in the same round trip as the partial sums and staged in LDS
+    constexpr int kHsW = sizeof(HypState) / sizeof(double), kPeW = sizeof(PoseEval) / sizeof(double);
+    static_assert(sizeof(HypState) % sizeof(double) == 0 && kMaxG * kHsW <= 3 * kEpiThreads &&
+                      kMaxG * kPeW <= kEpiThreads, "state prefetch shape");
+    const bool lm_mode = e.mode != MODE_DIAG;
+    const int nhs = lm_mode ? nh * kHsW : 0, npe = lm_mode ? nh * kPeW : 0;
+    const double *hs_src = reinterpret_cast<const double *>(e.hs + hb);
+    const double *pe_src = reinterpret_cast<const double *>(e.pose + hb);
+    double hsv[3], pev = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int w = threadIdx.x + k * kEpiThreads;
+        hsv[k] = w < nhs ? hs_src[w] : 0.0;
+    }
+    if ((int)threadIdx.x < npe) pev = pe_src[threadIdx.x];
     // The tile's records are read as float4 columns (4 adjacent values; a
     // hypothesis' 32 slots are 8 columns, the last holding the FP64 cost bits).
     // R threads per column: thread (r, q) sums the items r, r + R, r + 2R, ...
@@ -108,6 +124,15 @@ __global__ __launch_bounds__(kEpiThreads) void epilogue_kernel(EpilogueArgs e)
         dst[2] = cost_col ? 0.0 : a2;
         dst[3] = cost_col ? 0.0 : a3;
     }
+    {
+        double *hs_lds = reinterpret_cast<double *>(s_hs), *pe_lds = reinterpret_cast<double *>(s_pe);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int w = threadIdx.x + k * kEpiThreads;
+            if (w < nhs) hs_lds[w] = hsv[k];
+        }
+        if ((int)threadIdx.x < npe) pe_lds[threadIdx.x] = pev;
+    }
     __syncthreads();
     for (int tv = threadIdx.x; tv < stride; tv += kEpiThreads) {
         const int hh = tv / kNV, v = tv - hh * kNV;
@@ -119,11 +144,11 @@ __global__ __launch_bounds__(kEpiThreads) void epilogue_kernel(EpilogueArgs e)
     if (threadIdx.x == 0)
         atomicAdd(e.pairs, (unsigned long long)__popc(act) * (unsigned long long)f->lv[e.level].N);
     const int t = threadIdx.x;
-    if (t >= G || !((act >> t) & 1u)) return;
     const int gh = hb + t;
     const int m = h0 + t;
     const double *S = s_sum[t];
-    if (e.mode == MODE_DIAG) {
+    if (!lm_mode) {
+        if (t >= G || !((act >> t) & 1u)) return;
         double Hd[21], gd[6];
         for (int i = 0; i < 21; ++i) Hd[i] = S[i];
         for (int i = 0; i < 6; ++i) gd[i] = S[21 + i];
@@ -134,19 +159,26 @@ __global__ __launch_bounds__(kEpiThreads) void epilogue_kernel(EpilogueArgs e)
         f->diag_cost[m] = cost;
         f->diag_n[m] = (int)S[27];
         e.hlev[gh] = -1;
-    } else {
-        // the LM state lives in LDS while it is updated (a register copy of
-        // the whole state would not fit beside the reduction's registers)
-        HypState &s = s_hs[t];
-        PoseEval &p = s_pe[t];
-        s = e.hs[gh];
-        p = e.pose[gh];
+        return;
+    }
+    // the LM state lives in LDS while it is updated (a register copy of the
+    // whole state would not fit beside the reduction's registers)
+    if (t < G && ((act >> t) & 1u)) {
         int hl = e.level;
-        lm_advance(*f, s, S, p, hl);
-        e.hs[gh] = s;
-        e.pose[gh] = p;
+        lm_advance(*f, s_hs[t], S, s_pe[t], hl);
         e.hlev[gh] = hl;
         if (e.next_flag && hl == e.level) *e.next_flag = 1;   // the next pass of this level has work
+    }
+    __syncthreads();
+    // write the updated states back with the whole block (active hypotheses only)
+    {
+        double *hs_dst = reinterpret_cast<double *>(e.hs + hb);
+        double *pe_dst = reinterpret_cast<double *>(e.pose + hb);
+        const double *hs_lds = reinterpret_cast<const double *>(s_hs);
+        const double *pe_lds = reinterpret_cast<const double *>(s_pe);
+        for (int w = threadIdx.x; w < nhs; w += kEpiThreads)
+            if ((act >> (w / kHsW)) & 1u) hs_dst[w] = hs_lds[w];
+        if ((int)threadIdx.x < npe && ((act >> (threadIdx.x / kPeW)) & 1u)) pe_dst[threadIdx.x] = pe_lds[threadIdx.x];
     }
 }
 

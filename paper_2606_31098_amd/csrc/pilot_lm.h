@@ -78,9 +78,23 @@ __device__ inline void se3_mul(const double A[12], const double B[12], double ou
 }
 
 // (H + lam I) x = -g by Cholesky; false if a pivot is not positive/finite.
+// 1/sqrt(x) for finite x > 0: the hardware estimate refined by two Newton
+// steps (about one ulp).
+__device__ __forceinline__ double rsqrt64(double x)
+{
+    double r = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    r = r * fma(-h * r, r, 1.5);
+    r = r * fma(-h * r, r, 1.5);
+    return r;
+}
+
+// Cholesky factor of H + lam I and the two triangular solves.  Each column
+// keeps the reciprocal of its diagonal, 1/L_jj = 1/sqrt(s_jj), so the chain
+// of dependent operations holds six reciprocal square roots and no divisions.
 __device__ inline bool damped_solve(const double H[21], const double g[6], double lam, double x[6])
 {
-    double L[21];
+    double L[21], inv[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
 #pragma unroll
@@ -90,9 +104,10 @@ __device__ inline bool damped_solve(const double H[21], const double g[6], doubl
             for (int k = 0; k < j; ++k) s -= L[tri(k, i)] * L[tri(k, j)];
             if (i == j) {
                 if (!(s > 0.0) || !isfinite(s)) return false;
-                L[tri(i, i)] = sqrt(s);
+                inv[i] = rsqrt64(s);
+                L[tri(i, i)] = s * inv[i];
             } else {
-                L[tri(j, i)] = s / L[tri(j, j)];
+                L[tri(j, i)] = s * inv[j];
             }
         }
     }
@@ -103,14 +118,14 @@ __device__ inline bool damped_solve(const double H[21], const double g[6], doubl
         double s = -g[i];
 #pragma unroll
         for (int k = 0; k < i; ++k) s -= L[tri(k, i)] * y[k];
-        y[i] = s / L[tri(i, i)];
+        y[i] = s * inv[i];
     }
 #pragma unroll
     for (int i = 5; i >= 0; --i) {
         double s = y[i];
 #pragma unroll
         for (int k = i + 1; k < 6; ++k) s -= L[tri(i, k)] * x[k];
-        x[i] = s / L[tri(i, i)];
+        x[i] = s * inv[i];
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i)
