@@ -10,11 +10,58 @@ namespace pilot {
 // index of (a, b), a <= b, in the row-by-row upper triangle of a 6x6
 __host__ __device__ constexpr int tri(int a, int b) { return a * 6 - a * (a - 1) / 2 + (b - a); }
 
+// 1/x for finite nonzero x: the hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double recip64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
+// log(1 + q), and rx = 1/(1 + q), for the Cauchy loss.  x = 1 + q (rounded)
+// is split as 2^e m with m in [sqrt(1/2), sqrt(2)); log m = 2 atanh(t) with
+// t = (m - 1)/(m + 1), |t| < 0.172, summed through t^21 (the first omitted
+// term is below 2^-60 of the sum); the rounding of 1 + q adds (q - (x - 1))/x.
+// Within about 2 ulp of log1p for finite q > -0.5 (the loss argument is a
+// weighted squared residual, so q >= 0 up to rounding); a NaN or infinite q
+// gives a NaN, which the LM treats as the non-finite cost log1p would give.
+__device__ __forceinline__ double log1p_recip(double q, double &rx)
+{
+    constexpr double ln2_hi = 0x1.62e42fee00000p-1;   // ln 2 to 32 bits: e * ln2_hi is exact
+    constexpr double ln2_lo = 0x1.a39ef35793c76p-33;  // ln 2 - ln2_hi
+    const double x = 1.0 + q;
+    const double u = x - 1.0;                           // exact while x < 2^53 (beyond, corr is negligible)
+    rx = recip64(x);
+    const double corr = (q - u) * rx;
+    double m = __builtin_amdgcn_frexp_mant(x);
+    int e = __builtin_amdgcn_frexp_exp(x);
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double t = (m - 1.0) * recip64(m + 1.0);
+    const double t2 = t * t;
+    double p = 1.0 / 21.0;
+    p = fma(p, t2, 1.0 / 19.0);
+    p = fma(p, t2, 1.0 / 17.0);
+    p = fma(p, t2, 1.0 / 15.0);
+    p = fma(p, t2, 1.0 / 13.0);
+    p = fma(p, t2, 1.0 / 11.0);
+    p = fma(p, t2, 1.0 / 9.0);
+    p = fma(p, t2, 1.0 / 7.0);
+    p = fma(p, t2, 1.0 / 5.0);
+    p = fma(p, t2, 1.0 / 3.0);
+    const double s2 = 2.0 * t;
+    const double logm = fma(s2 * t2, p, s2);
+    const double de = (double)e;
+    return fma(de, ln2_hi, logm + fma(de, ln2_lo, corr));
+}
+
 __device__ __forceinline__ void robust_f64(int kind, double b, double s, double &rho, double &drho)
 {
-    if (kind == 0) {                       // Cauchy
-        rho = b * log1p(s / b);
-        drho = 1.0 / (1.0 + s / b);
+    if (kind == 0) {                       // Cauchy: b log(1 + s/b), weight 1/(1 + s/b)
+        rho = b * log1p_recip(s * (1.0 / b), drho);
     } else if (kind == 1) {                // Huber
         if (s <= b) {
             rho = s;
