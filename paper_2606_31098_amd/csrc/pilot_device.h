@@ -27,7 +27,7 @@ struct LevelDev {
     int iters, loss_kind;
     double loss_b;
     int dtype, pad;
-    // pass kernel variant 3: per-cell Gram matrices of the bilinear
+    // pass kernel variants 3 to 8: per-cell Gram matrices of the bilinear
     // coefficients, 10 doubles per cell (x0, y0) at index y0 W + x0
     const double *gram;
 };

@@ -34,7 +34,7 @@ hipError_t launch_init(const FrameDev *frames, int n_frames, int max_M, HypState
 hipError_t launch_reset_flags(int *flags, int n, int stride, hipStream_t s);
 
 // Per-cell Gram matrices of the bilinear coefficients of a feature map
-// (pass kernel variant 3): 10 doubles per cell, cells y0 W + x0.
+// (pass kernel variants 3 to 8): 10 doubles per cell, cells y0 W + x0.
 hipError_t launch_gram(const void *feat, int H, int W, int C, int dtype, double *gram, hipStream_t s);
 
 // Geo-anchor lift and reference-descriptor sampling (see pilot_lift).
