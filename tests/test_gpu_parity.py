@@ -219,6 +219,75 @@ def test_tile_shapes_and_kernel_variants_match_oracle(tmp_path, variant, G, dtyp
     assert not fails, fails
 
 
+@pytest.mark.parametrize("scale", [1e-9, 1e-6, 1e-3, 1.0, 1e3, 1e6, 1e9])
+def test_cauchy_loss_per_pair_matches_oracle(ctx, scale):
+    """The Cauchy loss of a pair (its log(1 + q) comes from a short atanh
+    series on the device) against the oracle's log1p: with four anchors the
+    cost of a hypothesis is four pair losses (and out-of-view penalties), and
+    sweeping the loss scale over 18 decades moves q = s / b from about 1e-8 to
+    1e10.  Poses are off the optimum, so the residuals are not a cancellation
+    of large terms and the FP64 chain is held to 1e-12 relative."""
+    from paper_2606_31098_amd.pilot import DeviceFrame
+    f = S.make_frame(2, 0, noise=True, N=4, M=8, level_shapes=((30, 40, 16), (60, 80, 32), (120, 160, 64)),
+                     iters=(6, 6, 6), dsm_side=128, seed=5)
+    for L in f.levels:
+        L.loss = (S.LOSS_CAUCHY, scale)
+    rng = np.random.default_rng(4)
+    poses = np.stack([oracle.compose(oracle.se3_exp(np.concatenate([rng.normal(0, 3, 3), rng.normal(0, 0.03, 3)])),
+                                     f.gt_pose) for _ in range(f.M)])
+    df = DeviceFrame(f)
+    of = oracle.OracleFrame(f)
+    say(f"cauchy scale={scale}")
+    for lvl in range(len(f.levels)):
+        _, _, cost, _ = ctx.linearize(df, lvl, torch.as_tensor(poses, device="cuda"))
+        cost = cost.cpu().numpy()
+        for m in range(f.M):
+            co = oracle.linearize(of, lvl, poses[m])[2]
+            assert abs(cost[m] - co) <= 1e-12 * abs(co), (lvl, m, cost[m], co)
+
+
+@pytest.mark.parametrize("dtype,variant", [("f32", 3), ("f32", 7), ("bf16", 5), ("bf16", 8)])
+def test_shared_gathers_leave_sums_bitwise_unchanged(tmp_path, dtype, variant):
+    """Hypotheses of a lane group that project into the same cell share one
+    gather and one set of tap sums.  The hypothesis in slot 3 of the first
+    tile (G = 8) is evaluated twice: once with slots 0-2 holding exact copies
+    of its pose (so its sums come from slot 0) and once with far-away poses
+    there (so it gathers itself).  Its normal equations and cost must be
+    bitwise identical, and match the oracle."""
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    d = 0 if dtype == "f32" else 1
+    f = pyramid_frame(seed=9, N=700, M=16, iters=(4, 4, 4))
+    if dtype == "bf16":
+        f = bf16_copy(f)
+    cache = tmp_path / "tune.txt"
+    with open(cache, "w") as fh:
+        for L in f.levels:
+            fh.write(f"C{L.C}_d{d}_N{_floor_log2(L.N)}_M{_floor_log2(f.M)}_P{_floor_log2(L.H * L.W)}_v3 "
+                     f"8 2 0 {variant}\n")
+    c = Context(0, tune_cache=str(cache))
+    rng = np.random.default_rng(2)
+    pert = lambda s_t, s_r: oracle.compose(oracle.se3_exp(np.concatenate([rng.normal(0, s_t, 3),
+                                                                           rng.normal(0, s_r, 3)])), f.gt_pose)
+    A = pert(0.5, 0.005)
+    others = [pert(4.0, 0.05) for _ in range(f.M)]
+    shared = np.stack([A, A, A, A] + others[4:])
+    alone = np.stack(others[:3] + [A] + others[4:])
+    mask_edges(f, np.concatenate([shared, alone]))
+    df = DeviceFrame(f, dtype=dtype)
+    of = oracle.OracleFrame(f)
+    say(f"shared gathers dtype={dtype} variant={variant}")
+    for lvl in range(3):
+        outs = []
+        for poses in (shared, alone):
+            H21, g, cost, n = c.linearize(df, lvl, torch.as_tensor(poses, device="cuda"))
+            outs.append((H21.cpu().numpy()[3].copy(), g.cpu().numpy()[3].copy(), cost.cpu().numpy()[3], n.cpu().numpy()[3]))
+        (Ha, ga, ca, na), (Hb, gb, cb, nb) = outs
+        assert np.array_equal(Ha, Hb) and np.array_equal(ga, gb) and ca == cb and na == nb, lvl
+        Ho, go, co, no = oracle.linearize(of, lvl, A)
+        err = rel_frobenius(np.concatenate([unpack_h21(Ha)[0], ga[:, None]], 1), np.concatenate([Ho, go[:, None]], 1))
+        assert err <= (1e-4 if variant in (5, 8) else NEQ_TOL), (lvl, err)
+
+
 # --------------------------------------------------------------------------- adaptive prior scales
 def _check_alpha(f, gpu, orc, rtol):
     ok = (orc["status"] != oracle.DEGENERATE) & (gpu["status"] != oracle.DEGENERATE)
