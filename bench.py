@@ -156,7 +156,15 @@ def roofline_leg(args, dfs, steps):
                                 "fabric_GBps": round(traffic / (avg_ms * 1e-3) / 1e9, 1),
                                 "fabric_frac_of_hbm": round(traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
                                 "l2_hit_rate": entry.get("l2_hit_rate"),
+                                "texture_addresser_busy": entry.get("texture_addresser_busy"),
+                                "texture_data_busy": entry.get("texture_data_busy"),
                                 "source": "profiles/pass_kernel_traffic.json (rocprofv3 --pmc, same kernel sources)"}
+                    # bytes that actually pass through L1 (the algorithmic bytes count every
+                    # pair's taps; hypotheses sharing a cell share one gather)
+                    l1 = entry.get("l1_bytes_per_launch")
+                    if l1:
+                        counters["l1_bytes_per_launch"] = l1
+                        counters["l1_frac_of_algorithmic"] = round(l1 / bytes_per_launch, 3)
         except (OSError, ValueError):
             traffic, counters = None, None
     C = dfs[0].s.level[fine].C
