@@ -32,18 +32,21 @@ hipError_t launch_pass(int C, int dtype, const TileConfig &tc, const PassArgs &a
 
 constexpr int kMaxG = 16;
 
-// One block per hypothesis tile: sums the tile's per-item partials in FP64
-// in item order (fixed, independent of what else shares the launch), then
-// one thread per hypothesis adds the prior terms and advances its LM state
-// (or writes the diagnostic system).
+// One block per hypothesis tile: kEpiThreads threads sum the tile's per-item
+// partials in FP64 in item order (fixed, independent of what else shares the
+// launch) while one more wave evaluates the prior terms at each hypothesis'
+// pending pose; then one thread per hypothesis adds the priors and advances
+// its LM state (or writes the diagnostic system).
 constexpr int kEpiThreads = 512;
+constexpr int kEpiBlock = kEpiThreads + 64;
 
-__global__ __launch_bounds__(kEpiThreads) void epilogue_kernel(EpilogueArgs e)
+__global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
 {
     __shared__ double s_sum[kMaxG][kNV];
     __shared__ double s_part[4 * kEpiThreads];     // R x G x kNV partial sums
     __shared__ HypState s_hs[kMaxG];
     __shared__ PoseEval s_pe[kMaxG];
+    __shared__ PriorTerms s_pri[kMaxG];
     // one block per tile: the tile's own mask (lane hh < nh of each wave reads
     // the level of hypothesis hb + hh, one load round trip) also covers a
     // level with no hypothesis left, so the run flag is not read here
@@ -57,81 +60,100 @@ __global__ __launch_bounds__(kEpiThreads) void epilogue_kernel(EpilogueArgs e)
     const int lv = lane < nh ? e.hlev[hb + lane] : -1;
     const unsigned act = __builtin_amdgcn_readfirstlane((unsigned)__ballot(lv == e.level));
     if (act == 0) return;
-    // LM states and poses of the tile's hypotheses, fetched by the whole block
+    // LM states and poses of the tile's hypotheses, fetched by the summing threads
     // in the same round trip as the partial sums and staged in LDS
     constexpr int kHsW = sizeof(HypState) / sizeof(double), kPeW = sizeof(PoseEval) / sizeof(double);
     static_assert(sizeof(HypState) % sizeof(double) == 0 && kMaxG * kHsW <= 3 * kEpiThreads &&
                       kMaxG * kPeW <= kEpiThreads, "state prefetch shape");
     const bool lm_mode = e.mode != MODE_DIAG;
     const int nhs = lm_mode ? nh * kHsW : 0, npe = lm_mode ? nh * kPeW : 0;
-    const double *hs_src = reinterpret_cast<const double *>(e.hs + hb);
-    const double *pe_src = reinterpret_cast<const double *>(e.pose + hb);
-    double hsv[3], pev = 0.0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int w = threadIdx.x + k * kEpiThreads;
-        hsv[k] = w < nhs ? hs_src[w] : 0.0;
-    }
-    if ((int)threadIdx.x < npe) pev = pe_src[threadIdx.x];
-    // The tile's records are read as float4 columns (4 adjacent values; a
-    // hypothesis' 32 slots are 8 columns, the last holding the FP64 cost bits).
-    // R threads per column: thread (r, q) sums the items r, r + R, r + 2R, ...
-    // of column q, issuing the loads of 8 items before adding them in item
-    // order; then the R partial sums are added in r order.  The order depends
-    // on the tile shape only.
     const int stride = G * kNV;
     const int Q = stride / 4;
     const int R = kEpiThreads / Q;
-    const int q = threadIdx.x % Q, r = threadIdx.x / Q;
-    {
-        const bool cost_col = (q % (kNV / 4)) == kCostSlot / 4;
-        const float4 *src = reinterpret_cast<const float4 *>(e.partials + (size_t)ti.first_item * stride) + q;
-        const int n = ti.n_ptiles;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int it = r;
-        for (; it + 7 * R < n; it += 8 * R) {
-            float4 x[8];
+    if (threadIdx.x >= kEpiThreads) {
+        // the prior wave: lane hh evaluates the prior terms of hypothesis hh at
+        // the pose the pass evaluated (the level's start pose, else the candidate)
+        const int hh = threadIdx.x - kEpiThreads;
+        if (lm_mode && hh < G && ((act >> hh) & 1u)) {
+            const HypState &hs = e.hs[hb + hh];
+            const bool start = hs.phase == PHASE_START;
+            double Tp[12];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) x[k] = src[(size_t)(it + k * R) * Q];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (cost_col) {
-                    a0 += __longlong_as_double((long long)((unsigned long long)__float_as_uint(x[k].x) |
-                                                           ((unsigned long long)__float_as_uint(x[k].y) << 32)));
-                } else {
-                    a0 += (double)x[k].x;
-                    a1 += (double)x[k].y;
-                    a2 += (double)x[k].z;
-                    a3 += (double)x[k].w;
-                }
+            for (int i = 0; i < 12; ++i) {
+                const double a = hs.T[i], c = hs.Tc[i];
+                Tp[i] = start ? a : c;
             }
+            PriorTerms p;
+            prior_terms(*f, Tp, p);
+            s_pri[hh] = p;
         }
-        for (; it < n; it += R) {
-            const float4 x = src[(size_t)it * Q];
-            if (cost_col) {
-                a0 += __longlong_as_double((long long)((unsigned long long)__float_as_uint(x.x) |
-                                                       ((unsigned long long)__float_as_uint(x.y) << 32)));
-            } else {
-                a0 += (double)x.x;
-                a1 += (double)x.y;
-                a2 += (double)x.z;
-                a3 += (double)x.w;
-            }
-        }
-        double *dst = s_part + (size_t)r * stride + 4 * q;
-        dst[0] = a0;
-        dst[1] = cost_col ? 0.0 : a1;
-        dst[2] = cost_col ? 0.0 : a2;
-        dst[3] = cost_col ? 0.0 : a3;
-    }
-    {
-        double *hs_lds = reinterpret_cast<double *>(s_hs), *pe_lds = reinterpret_cast<double *>(s_pe);
+    } else {
+        const double *hs_src = reinterpret_cast<const double *>(e.hs + hb);
+        const double *pe_src = reinterpret_cast<const double *>(e.pose + hb);
+        double hsv[3], pev = 0.0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int w = threadIdx.x + k * kEpiThreads;
-            if (w < nhs) hs_lds[w] = hsv[k];
+            hsv[k] = w < nhs ? hs_src[w] : 0.0;
         }
-        if ((int)threadIdx.x < npe) pe_lds[threadIdx.x] = pev;
+        if ((int)threadIdx.x < npe) pev = pe_src[threadIdx.x];
+        // The tile's records are read as float4 columns (4 adjacent values; a
+        // hypothesis' 32 slots are 8 columns, the last holding the FP64 cost bits).
+        // R threads per column: thread (r, q) sums the items r, r + R, r + 2R, ...
+        // of column q, issuing the loads of 8 items before adding them in item
+        // order; then the R partial sums are added in r order.  The order depends
+        // on the tile shape only.
+        const int q = threadIdx.x % Q, r = threadIdx.x / Q;
+        {
+            const bool cost_col = (q % (kNV / 4)) == kCostSlot / 4;
+            const float4 *src = reinterpret_cast<const float4 *>(e.partials + (size_t)ti.first_item * stride) + q;
+            const int n = ti.n_ptiles;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int it = r;
+            for (; it + 7 * R < n; it += 8 * R) {
+                float4 x[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) x[k] = src[(size_t)(it + k * R) * Q];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if (cost_col) {
+                        a0 += __longlong_as_double((long long)((unsigned long long)__float_as_uint(x[k].x) |
+                                                               ((unsigned long long)__float_as_uint(x[k].y) << 32)));
+                    } else {
+                        a0 += (double)x[k].x;
+                        a1 += (double)x[k].y;
+                        a2 += (double)x[k].z;
+                        a3 += (double)x[k].w;
+                    }
+                }
+            }
+            for (; it < n; it += R) {
+                const float4 x = src[(size_t)it * Q];
+                if (cost_col) {
+                    a0 += __longlong_as_double((long long)((unsigned long long)__float_as_uint(x.x) |
+                                                           ((unsigned long long)__float_as_uint(x.y) << 32)));
+                } else {
+                    a0 += (double)x.x;
+                    a1 += (double)x.y;
+                    a2 += (double)x.z;
+                    a3 += (double)x.w;
+                }
+            }
+            double *dst = s_part + (size_t)r * stride + 4 * q;
+            dst[0] = a0;
+            dst[1] = cost_col ? 0.0 : a1;
+            dst[2] = cost_col ? 0.0 : a2;
+            dst[3] = cost_col ? 0.0 : a3;
+        }
+        {
+            double *hs_lds = reinterpret_cast<double *>(s_hs), *pe_lds = reinterpret_cast<double *>(s_pe);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int w = threadIdx.x + k * kEpiThreads;
+                if (w < nhs) hs_lds[w] = hsv[k];
+            }
+            if ((int)threadIdx.x < npe) pe_lds[threadIdx.x] = pev;
+        }
     }
     __syncthreads();
     for (int tv = threadIdx.x; tv < stride; tv += kEpiThreads) {
@@ -165,7 +187,7 @@ __global__ __launch_bounds__(kEpiThreads) void epilogue_kernel(EpilogueArgs e)
     // whole state would not fit beside the reduction's registers)
     if (t < G && ((act >> t) & 1u)) {
         int hl = e.level;
-        lm_advance(*f, s_hs[t], S, s_pe[t], hl);
+        lm_advance(*f, s_hs[t], S, s_pri[t], s_pe[t], hl);
         e.hlev[gh] = hl;
         if (e.next_flag && hl == e.level) *e.next_flag = 1;   // the next pass of this level has work
     }
@@ -176,7 +198,7 @@ __global__ __launch_bounds__(kEpiThreads) void epilogue_kernel(EpilogueArgs e)
         double *pe_dst = reinterpret_cast<double *>(e.pose + hb);
         const double *hs_lds = reinterpret_cast<const double *>(s_hs);
         const double *pe_lds = reinterpret_cast<const double *>(s_pe);
-        for (int w = threadIdx.x; w < nhs; w += kEpiThreads)
+        for (int w = threadIdx.x; w < nhs; w += kEpiBlock)
             if ((act >> (w / kHsW)) & 1u) hs_dst[w] = hs_lds[w];
         if ((int)threadIdx.x < npe && ((act >> (threadIdx.x / kPeW)) & 1u)) pe_dst[threadIdx.x] = pe_lds[threadIdx.x];
     }
@@ -199,7 +221,7 @@ hipError_t launch_epilogue(const EpilogueArgs &e, hipStream_t s)
 {
     if (e.G > kMaxG) return hipErrorInvalidValue;
     if (e.n_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(epilogue_kernel, dim3(e.n_tiles), dim3(kEpiThreads), 0, s, e);
+    hipLaunchKernelGGL(epilogue_kernel, dim3(e.n_tiles), dim3(kEpiBlock), 0, s, e);
     return hipGetLastError();
 }
 

@@ -231,19 +231,37 @@ __device__ inline double range_residual(const FrameDev &f, const double T[12], d
     return P[2] - h;
 }
 
-// Add the gravity (Eq. (3)) and laser-range (Eqs. (4)-(6)) terms at pose T
-// with scales ag, ar (the lambda of Eq. (7), the alpha of the supplement's
-// H_total, g_total).
-__device__ inline void add_priors(const FrameDev &f, const double T[12], double ag, double ar, double H[21],
+// Prior residuals at one pose with their robust losses, before any scale:
+// gravity (Eq. (3)) and laser range (Eqs. (4)-(6)).  They depend on the pose
+// alone, so the epilogue can evaluate them while the photometric sums of the
+// same pose are still being reduced.
+struct PriorTerms {
+    double gc[3], rg[3], sg, rho_g, drho_g;   // gravity: R g_world, residual, |r|^2, loss
+    double J[6], rr, rho_r, drho_r;           // range: Jacobian row, residual, loss
+};
+
+__device__ inline void prior_terms(const FrameDev &f, const double T[12], PriorTerms &p)
+{
+    if (f.use_g) {
+        gravity_residual(f, T, p.gc, p.rg);
+        p.sg = p.rg[0] * p.rg[0] + p.rg[1] * p.rg[1] + p.rg[2] * p.rg[2];
+        robust_f64(f.grav_kind, f.grav_b, p.sg, p.rho_g, p.drho_g);
+    }
+    if (f.use_r) {
+        p.rr = range_residual(f, T, p.J);
+        robust_f64(f.range_kind, f.range_b, p.rr * p.rr, p.rho_r, p.drho_r);
+    }
+}
+
+// Add the gravity and range terms with scales ag, ar (the lambda of Eq. (7),
+// the alpha of the supplement's H_total, g_total).
+__device__ inline void add_priors(const FrameDev &f, const PriorTerms &p, double ag, double ar, double H[21],
                                   double g[6], double &cost)
 {
     if (f.use_g) {
-        double gc[3], r[3];
-        gravity_residual(f, T, gc, r);
-        double rho, drho;
-        robust_f64(f.grav_kind, f.grav_b, r[0] * r[0] + r[1] * r[1] + r[2] * r[2], rho, drho);
-        cost += ag * rho;
-        const double W = ag * drho;
+        cost += ag * p.rho_g;
+        const double W = ag * p.drho_g;
+        const double *gc = p.gc, *r = p.rg;
         // J^T J = |gc|^2 I - gc gc^T,  J^T r = gc x r  (rotation block)
         const double n2 = gc[0] * gc[0] + gc[1] * gc[1] + gc[2] * gc[2];
 #pragma unroll
@@ -255,27 +273,31 @@ __device__ inline void add_priors(const FrameDev &f, const double T[12], double 
         g[5] += W * (gc[0] * r[1] - gc[1] * r[0]);
     }
     if (f.use_r) {
-        double J[6];
-        const double r = range_residual(f, T, J);
-        double rho, drho;
-        robust_f64(f.range_kind, f.range_b, r * r, rho, drho);
-        cost += ar * rho;
-        const double W = ar * drho;
+        cost += ar * p.rho_r;
+        const double W = ar * p.drho_r;
 #pragma unroll
         for (int a = 0; a < 6; ++a) {
 #pragma unroll
-            for (int b = a; b < 6; ++b) H[tri(a, b)] += W * J[a] * J[b];
-            g[a] += W * J[a] * r;
+            for (int b = a; b < 6; ++b) H[tri(a, b)] += W * p.J[a] * p.J[b];
+            g[a] += W * p.J[a] * p.rr;
         }
     }
 }
 
-// Prior scales at pose T given the visual gradient gv (supplement,
-// Sensor-Prior Fusion in LM): each enabled prior's base scale is reduced so
-// that its gradient does not exceed alpha_ratio times the visual one, and by
-// (gate / |r|)^2 when its residual exceeds the gate.  Fixed scales unless
-// f.adaptive; 0 for a disabled prior.
-__device__ inline void prior_scales(const FrameDev &f, const double T[12], const double gv[6], double alpha[2])
+__device__ inline void add_priors(const FrameDev &f, const double T[12], double ag, double ar, double H[21],
+                                  double g[6], double &cost)
+{
+    PriorTerms p;
+    prior_terms(f, T, p);
+    add_priors(f, p, ag, ar, H, g, cost);
+}
+
+// Prior scales from the prior terms at the level's starting pose and the
+// visual gradient gv there (supplement, Sensor-Prior Fusion in LM): each
+// enabled prior's base scale is reduced so that its gradient does not exceed
+// alpha_ratio times the visual one, and by (gate / |r|)^2 when its residual
+// exceeds the gate.  Fixed scales unless f.adaptive; 0 for a disabled prior.
+__device__ inline void prior_scales(const FrameDev &f, const PriorTerms &p, const double gv[6], double alpha[2])
 {
     alpha[0] = f.use_g ? f.lam_imu : 0.0;
     alpha[1] = f.use_r ? f.lam_range : 0.0;
@@ -285,27 +307,21 @@ __device__ inline void prior_scales(const FrameDev &f, const double T[12], const
     for (int a = 0; a < 6; ++a) nv += gv[a] * gv[a];
     nv = sqrt(nv);
     if (f.use_g) {
-        double gc[3], r[3], rho, drho;
-        gravity_residual(f, T, gc, r);
-        const double s = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        robust_f64(f.grav_kind, f.grav_b, s, rho, drho);
+        const double *gc = p.gc, *r = p.rg;
         // unit-scale gradient drho * J^T r = drho * (0, gc x r)
         const double c0 = gc[1] * r[2] - gc[2] * r[1], c1 = gc[2] * r[0] - gc[0] * r[2],
                      c2 = gc[0] * r[1] - gc[1] * r[0];
-        const double gn = fabs(drho) * sqrt(c0 * c0 + c1 * c1 + c2 * c2);
-        const double rn = sqrt(s);
+        const double gn = fabs(p.drho_g) * sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+        const double rn = sqrt(p.sg);
         if (f.alpha_ratio > 0.0 && f.lam_imu * gn > f.alpha_ratio * nv) alpha[0] *= f.alpha_ratio * nv / (f.lam_imu * gn);
         if (f.grav_gate > 0.0 && rn > f.grav_gate) alpha[0] *= (f.grav_gate / rn) * (f.grav_gate / rn);
     }
     if (f.use_r) {
-        double J[6], rho, drho;
-        const double r = range_residual(f, T, J);
-        robust_f64(f.range_kind, f.range_b, r * r, rho, drho);
         double n2 = 0.0;
 #pragma unroll
-        for (int a = 0; a < 6; ++a) n2 += J[a] * J[a];
-        const double gn = fabs(drho * r) * sqrt(n2);
-        const double rn = fabs(r);
+        for (int a = 0; a < 6; ++a) n2 += p.J[a] * p.J[a];
+        const double gn = fabs(p.drho_r * p.rr) * sqrt(n2);
+        const double rn = fabs(p.rr);
         if (f.alpha_ratio > 0.0 && f.lam_range * gn > f.alpha_ratio * nv)
             alpha[1] *= f.alpha_ratio * nv / (f.lam_range * gn);
         if (f.range_gate > 0.0 && rn > f.range_gate) alpha[1] *= (f.range_gate / rn) * (f.range_gate / rn);
@@ -368,9 +384,11 @@ __device__ inline void propose(const FrameDev &f, HypState &s, PoseEval &p32, in
     }
 }
 
-// Consume one evaluation (photo sums S: H21, g6, count, cost) of the
-// hypothesis at its pending pose and advance its LM state.
-__device__ inline void lm_advance(const FrameDev &f, HypState &s, const double *S, PoseEval &p32, int &hlev)
+// Consume one evaluation (photo sums S: H21, g6, count, cost; prior terms P)
+// of the hypothesis at its pending pose (T at a level start, else Tc) and
+// advance its LM state.
+__device__ inline void lm_advance(const FrameDev &f, HypState &s, const double *S, const PriorTerms &P, PoseEval &p32,
+                                  int &hlev)
 {
     double H[21], g[6];
 #pragma unroll
@@ -379,11 +397,10 @@ __device__ inline void lm_advance(const FrameDev &f, HypState &s, const double *
     for (int i = 0; i < 6; ++i) g[i] = S[21 + i];
     double cost = S[kCostSlot];
     const int n = (int)S[27];
-    const double *Tp = (s.phase == PHASE_START) ? s.T : s.Tc;
     // the prior scales are set at the level's starting pose and held for the
     // level, so its objective is fixed and a cost decrease is well defined
-    if (s.phase == PHASE_START) prior_scales(f, Tp, g, s.alpha);
-    add_priors(f, Tp, s.alpha[0], s.alpha[1], H, g, cost);
+    if (s.phase == PHASE_START) prior_scales(f, P, g, s.alpha);
+    add_priors(f, P, s.alpha[0], s.alpha[1], H, g, cost);
 
     bool finite = isfinite(cost);
 #pragma unroll
