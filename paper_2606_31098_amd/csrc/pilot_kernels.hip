@@ -48,8 +48,11 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
     __shared__ PoseEval s_pe[kMaxG];
     __shared__ PriorTerms s_pri[kMaxG];
     // one block per tile: the tile's own mask (lane hh < nh of each wave reads
-    // the level of hypothesis hb + hh, one load round trip) also covers a
-    // level with no hypothesis left, so the run flag is not read here
+    // the level of hypothesis hb + hh) also covers a level with no hypothesis
+    // left, so the run flag is not read here.  The levels, the LM states, the
+    // poses and the partial sums are all fetched in one load round trip: the
+    // loads below do not wait for the mask, which is only tested (uniformly
+    // over the block) before the first barrier.
     const TileItem ti = e.tiles[blockIdx.x];
     const FrameDev *f = e.frames + ti.frame;
     const int G = e.G;
@@ -58,10 +61,8 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
     const int nh = ti.nh;
     const int lane = threadIdx.x & 63;
     const int lv = lane < nh ? e.hlev[hb + lane] : -1;
-    const unsigned act = __builtin_amdgcn_readfirstlane((unsigned)__ballot(lv == e.level));
-    if (act == 0) return;
-    // LM states and poses of the tile's hypotheses, fetched by the summing threads
-    // in the same round trip as the partial sums and staged in LDS
+    // LM states and poses of the tile's hypotheses, fetched by the summing
+    // threads and staged in LDS
     constexpr int kHsW = sizeof(HypState) / sizeof(double), kPeW = sizeof(PoseEval) / sizeof(double);
     static_assert(sizeof(HypState) % sizeof(double) == 0 && kMaxG * kHsW <= 3 * kEpiThreads &&
                       kMaxG * kPeW <= kEpiThreads, "state prefetch shape");
@@ -72,9 +73,11 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
     const int R = kEpiThreads / Q;
     if (threadIdx.x >= kEpiThreads) {
         // the prior wave: lane hh evaluates the prior terms of hypothesis hh at
-        // the pose the pass evaluated (the level's start pose, else the candidate)
+        // the pose the pass evaluated (the level's start pose, else the
+        // candidate); inactive hypotheses are evaluated too (their terms go
+        // unused: the DSM lookup clamps to the grid whatever the pose)
         const int hh = threadIdx.x - kEpiThreads;
-        if (lm_mode && hh < G && ((act >> hh) & 1u)) {
+        if (lm_mode && hh < nh) {
             const HypState &hs = e.hs[hb + hh];
             const bool start = hs.phase == PHASE_START;
             double Tp[12];
@@ -155,6 +158,8 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
             if ((int)threadIdx.x < npe) pe_lds[threadIdx.x] = pev;
         }
     }
+    const unsigned act = __builtin_amdgcn_readfirstlane((unsigned)__ballot(lv == e.level));
+    if (act == 0) return;
     __syncthreads();
     for (int tv = threadIdx.x; tv < stride; tv += kEpiThreads) {
         const int hh = tv / kNV, v = tv - hh * kNV;
