@@ -47,6 +47,7 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
     __shared__ HypState s_hs[kMaxG];
     __shared__ PoseEval s_pe[kMaxG];
     __shared__ PriorTerms s_pri[kMaxG];
+    __shared__ FrameDev s_f;
     // one block per tile: the tile's own mask (lane hh < nh of each wave reads
     // the level of hypothesis hb + hh) also covers a level with no hypothesis
     // left, so the run flag is not read here.  The levels, the LM states, the
@@ -61,9 +62,12 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
     const int nh = ti.nh;
     const int lane = threadIdx.x & 63;
     const int lv = lane < nh ? e.hlev[hb + lane] : -1;
-    // LM states and poses of the tile's hypotheses, fetched by the summing
-    // threads and staged in LDS
+    // LM states and poses of the tile's hypotheses and the frame's constants,
+    // fetched by the summing threads and staged in LDS (the LM step then reads
+    // its parameters there rather than one dependent global load at a time)
     constexpr int kHsW = sizeof(HypState) / sizeof(double), kPeW = sizeof(PoseEval) / sizeof(double);
+    constexpr int kFdW = sizeof(FrameDev) / sizeof(unsigned long long);
+    static_assert(sizeof(FrameDev) % sizeof(unsigned long long) == 0 && kFdW <= kEpiThreads, "frame staging shape");
     static_assert(sizeof(HypState) % sizeof(double) == 0 && kMaxG * kHsW <= 3 * kEpiThreads &&
                       kMaxG * kPeW <= kEpiThreads, "state prefetch shape");
     const bool lm_mode = e.mode != MODE_DIAG;
@@ -100,6 +104,8 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
             hsv[k] = w < nhs ? hs_src[w] : 0.0;
         }
         if ((int)threadIdx.x < npe) pev = pe_src[threadIdx.x];
+        unsigned long long fdv = 0;
+        if (threadIdx.x < kFdW) fdv = reinterpret_cast<const unsigned long long *>(f)[threadIdx.x];
         // The tile's records are read as float4 columns (4 adjacent values; a
         // hypothesis' 32 slots are 8 columns, the last holding the FP64 cost bits).
         // R threads per column: thread (r, q) sums the items r, r + R, r + 2R, ...
@@ -156,6 +162,7 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
                 if (w < nhs) hs_lds[w] = hsv[k];
             }
             if ((int)threadIdx.x < npe) pe_lds[threadIdx.x] = pev;
+            if (threadIdx.x < kFdW) reinterpret_cast<unsigned long long *>(&s_f)[threadIdx.x] = fdv;
         }
     }
     const unsigned act = __builtin_amdgcn_readfirstlane((unsigned)__ballot(lv == e.level));
@@ -168,8 +175,8 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
         s_sum[hh][v] = sum;
     }
     __syncthreads();
-    if (threadIdx.x == 0)
-        atomicAdd(e.pairs, (unsigned long long)__popc(act) * (unsigned long long)f->lv[e.level].N);
+    if (threadIdx.x == kEpiThreads)   // the prior wave: not on an LM thread's path
+        atomicAdd(e.pairs, (unsigned long long)__popc(act) * (unsigned long long)s_f.lv[e.level].N);
     const int t = threadIdx.x;
     const int gh = hb + t;
     const int m = h0 + t;
@@ -192,7 +199,7 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
     // whole state would not fit beside the reduction's registers)
     if (t < G && ((act >> t) & 1u)) {
         int hl = e.level;
-        lm_advance(*f, s_hs[t], S, s_pri[t], s_pe[t], hl);
+        lm_advance(s_f, s_hs[t], S, s_pri[t], s_pe[t], hl);
         e.hlev[gh] = hl;
         if (e.next_flag && hl == e.level) *e.next_flag = 1;   // the next pass of this level has work
     }
