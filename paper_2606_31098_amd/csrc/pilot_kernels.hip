@@ -464,11 +464,16 @@ __device__ __forceinline__ double quad_sum(double v)
 }
 
 // A lane quad per cell: lane q of the quad takes channels 4q + 16k .. +3, so
-// the quad's loads of one tap are one contiguous 64-byte run.
+// the quad's loads of one tap are one contiguous 64-byte run.  Blocks are
+// dealt to the 8 XCDs round-robin; the block index is remapped so that each
+// XCD walks one contiguous band of cell rows, and the map row shared by two
+// consecutive cell rows is read into one XCD's L2 rather than two.
 template <int DT>
 __global__ __launch_bounds__(256) void gram_kernel(const void *feat, int H, int W, int C, double *gram)
 {
-    const long cell = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+    const unsigned nb = gridDim.x, xcd = blockIdx.x % 8u, per = nb / 8u, rem = nb % 8u;
+    const unsigned lb = xcd * per + min(xcd, rem) + blockIdx.x / 8u;
+    const long cell = ((long)lb * blockDim.x + threadIdx.x) >> 2;
     const int q = threadIdx.x & 3;
     const bool live = cell < (long)H * W;
     const int y0 = live ? (int)(cell / W) : 0, x0 = live ? (int)(cell - (long)y0 * W) : 0;
