@@ -25,13 +25,13 @@ hipError_t launch_pass(int C, int dtype, const TileConfig &tc, const PassArgs &a
 hipError_t launch_epilogue(const EpilogueArgs &e, hipStream_t s);
 
 // Initialise hypothesis state of frames[0..n_frames) from their poses_in
-// (mode LM) or from `diag_poses` at `diag_level` (mode DIAG, one frame).
+// (mode LM) or from `diag_poses` at `diag_level` (mode DIAG, one frame), and,
+// when `flags` is given, the solve's pass flags (see EpilogueArgs::next_flag):
+// n_flags flags, flag_stride per level.
 hipError_t launch_init(const FrameDev *frames, int n_frames, int max_M, HypState *hs,
                        PoseEval *pose, int *hlev, int mode, const double *diag_poses,
-                       int diag_level, hipStream_t s);
-
-// Pass flags of a solve (see EpilogueArgs::next_flag): n flags, stride per level.
-hipError_t launch_reset_flags(int *flags, int n, int stride, hipStream_t s);
+                       int diag_level, hipStream_t s, int *flags = nullptr, int n_flags = 0,
+                       int flag_stride = 1);
 
 // Per-cell Gram matrices of the bilinear coefficients of a feature map
 // (pass kernel variants 3 to 8): 10 doubles per cell, cells y0 W + x0.

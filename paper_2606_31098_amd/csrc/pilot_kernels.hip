@@ -216,19 +216,6 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
     }
 }
 
-// Pass flags of a solve: flag (l, 0) = 1 (every level's first pass runs),
-// the others 0 until an epilogue raises them.
-__global__ void reset_flags_kernel(int *flags, int n, int stride)
-{
-    for (int i = threadIdx.x; i < n; i += blockDim.x) flags[i] = (i % stride == 0) ? 1 : 0;
-}
-
-hipError_t launch_reset_flags(int *flags, int n, int stride, hipStream_t s)
-{
-    hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(256), 0, s, flags, n, stride);
-    return hipGetLastError();
-}
-
 hipError_t launch_epilogue(const EpilogueArgs &e, hipStream_t s)
 {
     if (e.G > kMaxG) return hipErrorInvalidValue;
@@ -237,11 +224,16 @@ hipError_t launch_epilogue(const EpilogueArgs &e, hipStream_t s)
     return hipGetLastError();
 }
 
-// One thread per hypothesis; blockIdx.y selects the frame.
+// One thread per hypothesis; blockIdx.y selects the frame.  Block (0, 0) also
+// sets the solve's pass flags, if given: flag (l, 0) = 1 (every level's first
+// pass runs), the others 0 until an epilogue raises them.
 __global__ __launch_bounds__(256) void init_kernel(const FrameDev *frames, HypState *hs, PoseEval *pose,
-                                                    int *hlev, int mode, const double *dposes, int dlevel)
+                                                    int *hlev, int mode, const double *dposes, int dlevel,
+                                                    int *flags, int n_flags, int flag_stride)
 {
     const FrameDev &f = frames[blockIdx.y];
+    if (flags && blockIdx.x == 0 && blockIdx.y == 0)
+        for (int i = threadIdx.x; i < n_flags; i += blockDim.x) flags[i] = (i % flag_stride == 0) ? 1 : 0;
     if (blockIdx.x == 0 && threadIdx.x == 0 && f.done_flag) *f.done_flag = 0;
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= f.M) return;
@@ -307,10 +299,13 @@ __global__ __launch_bounds__(256) void init_kernel(const FrameDev *frames, HypSt
 }
 
 hipError_t launch_init(const FrameDev *frames, int n_frames, int max_M, HypState *hs, PoseEval *pose,
-                       int *hlev, int mode, const double *diag_poses, int diag_level, hipStream_t s)
+                       int *hlev, int mode, const double *diag_poses, int diag_level, hipStream_t s, int *flags,
+                       int n_flags, int flag_stride)
 {
+    if (flags && (n_flags < 0 || flag_stride <= 0)) return hipErrorInvalidValue;
     dim3 grid((max_M + 255) / 256, n_frames), block(256);
-    hipLaunchKernelGGL(init_kernel, grid, block, 0, s, frames, hs, pose, hlev, mode, diag_poses, diag_level);
+    hipLaunchKernelGGL(init_kernel, grid, block, 0, s, frames, hs, pose, hlev, mode, diag_poses, diag_level, flags,
+                       n_flags, flag_stride);
     return hipGetLastError();
 }
 

@@ -697,9 +697,9 @@ int enqueue_gram(pilot_ctx *ctx, const Plan &plan, hipStream_t s)
 int enqueue_schedule(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, hipStream_t s, bool timed)
 {
     if (int rc = enqueue_gram(ctx, plan, s)) return rc;
-    HIPCHK(ctx, launch_reset_flags((int *)ctx->passflag.p, PILOT_MAX_LEVELS * plan.flag_stride, plan.flag_stride, s));
     HIPCHK(ctx, launch_init(dp.frames, (int)plan.frames.size(), plan.max_M, (HypState *)ctx->hs.p,
-                            (PoseEval *)ctx->pose.p, (int *)ctx->hlev.p, MODE_LM, nullptr, 0, s));
+                            (PoseEval *)ctx->pose.p, (int *)ctx->hlev.p, MODE_LM, nullptr, 0, s,
+                            (int *)ctx->passflag.p, PILOT_MAX_LEVELS * plan.flag_stride, plan.flag_stride));
     for (int l = 0; l < plan.max_levels; ++l) {
         int maxp = 0;
         for (const LaunchGroup &g : plan.groups)
