@@ -132,6 +132,8 @@ struct EpilogueArgs {
     HypState *hs;
     unsigned long long *pairs;   // evaluated anchor x hypothesis pairs of this launch's class
     int *next_flag;              // NULL, or set to 1 when a hypothesis stays at this level
+    int mask_first;              // test the tile mask before fetching the partial sums (launches
+                                 // where most tiles are at other levels), else after
 };
 
 }  // namespace pilot

@@ -50,10 +50,12 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
     __shared__ FrameDev s_f;
     // one block per tile: the tile's own mask (lane hh < nh of each wave reads
     // the level of hypothesis hb + hh) also covers a level with no hypothesis
-    // left, so the run flag is not read here.  The levels, the LM states, the
-    // poses and the partial sums are all fetched in one load round trip: the
-    // loads below do not wait for the mask, which is only tested (uniformly
-    // over the block) before the first barrier.
+    // left, so the run flag is not read here.  By default the levels, the LM
+    // states, the poses and the partial sums are all fetched in one load round
+    // trip: the loads below do not wait for the mask, which is only tested
+    // (uniformly over the block) before the first barrier.  With mask_first
+    // (launches where most tiles have no hypothesis at the level) an inactive
+    // tile exits after the level loads instead.
     const TileItem ti = e.tiles[blockIdx.x];
     const FrameDev *f = e.frames + ti.frame;
     const int G = e.G;
@@ -62,6 +64,7 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
     const int nh = ti.nh;
     const int lane = threadIdx.x & 63;
     const int lv = lane < nh ? e.hlev[hb + lane] : -1;
+    if (e.mask_first && __builtin_amdgcn_readfirstlane((unsigned)__ballot(lv == e.level)) == 0) return;
     // LM states and poses of the tile's hypotheses and the frame's constants,
     // fetched by the summing threads and staged in LDS (the LM step then reads
     // its parameters there rather than one dependent global load at a time)

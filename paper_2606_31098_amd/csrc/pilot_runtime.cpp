@@ -635,7 +635,8 @@ int ensure_state(pilot_ctx *ctx, Plan &plan)
 
 // Enqueue one pass (pass kernel + epilogue) of a launch group.
 int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const LaunchGroup &g, int mode,
-                 hipStream_t s, bool timed, const int *run_flag = nullptr, int *next_flag = nullptr)
+                 hipStream_t s, bool timed, const int *run_flag = nullptr, int *next_flag = nullptr,
+                 bool mask_first = false)
 {
     if (uses_gram(g.tc))                       // every frame of the group needs its Gram table
         for (int t = g.tile_off; t < g.tile_off + g.n_tiles; ++t)
@@ -677,6 +678,7 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Laun
     e.hs = (HypState *)ctx->hs.p;
     e.pairs = (unsigned long long *)ctx->pairs.p + g.stat_class;
     e.next_flag = next_flag;
+    e.mask_first = mask_first ? 1 : 0;
     HIPCHK(ctx, launch_epilogue(e, s));
     ctx->launches[g.stat_class]++;
     return PILOT_OK;
@@ -1423,10 +1425,12 @@ int pilot_step(pilot_ctx *ctx)
     dp.frames = (FrameDev *)ctx->s_frames.p;
     dp.items = (WorkItem *)ctx->s_desc.p;
     dp.tiles = (TileItem *)((char *)ctx->s_desc.p + ib);
+    // a serving step runs every level over every active slot, so most tiles of
+    // a launch are at other levels: its epilogues test the tile mask first
     for (int l = 0; l < PILOT_MAX_LEVELS; ++l)
         for (const LaunchGroup &g : plan.groups)
             if (g.level == l && (rc = enqueue_pass(ctx, plan, dp, g, MODE_LM, ctx->stream,
-                                                   (ctx->flags & PILOT_FLAG_PROFILE) != 0)))
+                                                   (ctx->flags & PILOT_FLAG_PROFILE) != 0, nullptr, nullptr, true)))
                 return rc;
     bool prunes = false;
     for (const ServingSlot &sl : ctx->slots) prunes = prunes || (sl.active && sl.frame.keep_top > 0);
