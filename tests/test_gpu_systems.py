@@ -76,6 +76,34 @@ def test_graph_replays_match_eager(alone):
             assert same(outs[k][i], ref[i]) and same(eager[i], ref[i]), (k, i)
 
 
+def test_repeated_solves_follow_changed_frame_parameters(alone):
+    """A context re-solving the same frame (same device buffers and plan
+    shape, so one captured graph) uploads the frame's descriptors again when a
+    scalar parameter changed and skips the copy when nothing did: every result
+    equals a fresh context's solve with the same parameters."""
+    from paper_2606_31098_amd.pilot import Context
+    fr, dfs, ref = alone
+    d = dfs[0]
+    ctx = Context(0)
+    say("repeated solves with a changed damping parameter")
+    r0 = as_np(ctx.solve([d])[0])
+    tau0 = d.s.tau
+    try:
+        d.s.tau = tau0 * 1e4
+        r1 = as_np(ctx.solve([d])[0])
+        r1b = as_np(ctx.solve([d])[0])
+        fresh = as_np(Context(0).solve([d])[0])
+    finally:
+        d.s.tau = tau0
+    r2 = as_np(ctx.solve([d])[0])
+    torch.cuda.synchronize()
+    assert same(r0, ref[0])
+    assert same(r1, fresh) and same(r1b, fresh)
+    assert not same(r1, ref[0])           # the changed damping took effect
+    assert same(r2, ref[0])
+    assert ctx.stats().graph_captures == 1
+
+
 def test_batched_frames_match_oracle(alone):
     fr, dfs, ref = alone
     for i, f in enumerate(fr):
