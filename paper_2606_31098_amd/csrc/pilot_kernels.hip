@@ -322,29 +322,54 @@ __global__ __launch_bounds__(256) void finalize_kernel(const FrameDev *frames, c
     if (f.M <= 0) return;                          // unused serving slot
     __shared__ double s_cost[256];
     __shared__ int s_idx[256];
-    __shared__ int s_skip;
-    if (threadIdx.x == 0) s_skip = (f.done_flag && *f.done_flag) ? 1 : 0;
-    __syncthreads();
-    if (s_skip) return;
+    // The done flag, the levels and the states of the first 256 hypotheses are
+    // fetched in one load round trip; nothing is written unless the frame is
+    // not yet finalised and none of its hypotheses is still running.
+    const int done = f.done_flag ? *f.done_flag : 0;
     int pending = 0;
     for (int m = threadIdx.x; m < f.M; m += blockDim.x) pending |= (hlev[f.hyp_base + m] != -1);
+    double T0[12], cost0 = 0.0, al0 = 0.0, al1 = 0.0;
+    int it0 = 0, st0 = 0;
+    const bool has0 = (int)threadIdx.x < f.M;
+    if (has0) {
+        const HypState &s = hs[f.hyp_base + threadIdx.x];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) T0[i] = s.T[i];
+        cost0 = s.cost;
+        it0 = s.it_total;
+        st0 = s.status;
+        al0 = s.alpha[0];
+        al1 = s.alpha[1];
+    }
+    if (done) return;                              // the same value in every thread
     if (__syncthreads_or(pending)) return;
 
     double bc = 0.0;
     int bi = -1;
     for (int m = threadIdx.x; m < f.M; m += blockDim.x) {
-        const HypState &s = hs[f.hyp_base + m];
+        double T[12], cost, a0, a1;
+        int it, st;
+        if (m == (int)threadIdx.x) {
 #pragma unroll
-        for (int i = 0; i < 12; ++i) f.poses_out[(size_t)12 * m + i] = s.T[i];
-        f.cost_out[m] = s.cost;
-        f.iters_out[m] = s.it_total;
-        f.status_out[m] = s.status;
-        if (f.alpha_out) {
-            f.alpha_out[2 * m] = s.alpha[0];
-            f.alpha_out[2 * m + 1] = s.alpha[1];
+            for (int i = 0; i < 12; ++i) T[i] = T0[i];
+            cost = cost0, it = it0, st = st0, a0 = al0, a1 = al1;
+        } else {
+            const HypState &s = hs[f.hyp_base + m];
+#pragma unroll
+            for (int i = 0; i < 12; ++i) T[i] = s.T[i];
+            cost = s.cost, it = s.it_total, st = s.status, a0 = s.alpha[0], a1 = s.alpha[1];
         }
-        if (s.status != ST_DEGENERATE && s.status != ST_PRUNED && isfinite(s.cost) && (bi < 0 || s.cost < bc)) {
-            bc = s.cost;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) f.poses_out[(size_t)12 * m + i] = T[i];
+        f.cost_out[m] = cost;
+        f.iters_out[m] = it;
+        f.status_out[m] = st;
+        if (f.alpha_out) {
+            f.alpha_out[2 * m] = a0;
+            f.alpha_out[2 * m + 1] = a1;
+        }
+        if (st != ST_DEGENERATE && st != ST_PRUNED && isfinite(cost) && (bi < 0 || cost < bc)) {
+            bc = cost;
             bi = m;
         }
     }
