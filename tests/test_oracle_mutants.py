@@ -41,6 +41,11 @@ MUTANTS = {
                                "const int flat = 0;"),
     "cost_tolerance_absolute": ("const int flat = f->cost_tol > 0.0 && fabs(cc - c) <= f->cost_tol * c;",
                                 "const int flat = f->cost_tol > 0.0 && fabs(cc - c) <= f->cost_tol;"),
+    "qconf_uv_transposed": ("orc_bilinear(L->qconf, L->H, L->W, 1, u, v, &q, &qu, &qv);",
+                            "orc_bilinear(L->qconf, L->H, L->W, 1, v, u, &q, &qu, &qv);"),
+    "qconf_dropped": ("wq = q;", "wq = 1.0;"),
+    "weight_outside_rho": ("        s *= w;\n        orc_robust(L->loss_kind, L->loss_scale, s, &rho, &drho);\n        c += rho;",
+                           "        orc_robust(L->loss_kind, L->loss_scale, s, &rho, &drho);\n        c += w * rho;"),
     "scales_from_candidate_gradient": ("orc_prior_scales(f, st->T, g, st->alpha);",
                                        "orc_prior_scales(f, st->T, H, st->alpha);"),
 }

@@ -192,6 +192,119 @@ def test_out_of_view_penalty():
     assert c == pytest.approx(8 * b * math.log1p(2.0 / b), rel=1e-14)
 
 
+# ---------------------------------------------------------------- confidence weights
+def _in_view_frame(seed, poses, margin=1.5, N=120, loss=None):
+    """A two-level frame without priors whose anchors all project at least
+    `margin` px inside every level under every pose in `poses` (so no anchor
+    takes the out-of-view penalty, which carries the per-anchor weight only)."""
+    f = small_frame(seed=seed, N=N, M=1)
+    f.use_gravity = f.use_range = 0
+    keep = np.ones(N, bool)
+    for L in f.levels:
+        P = np.stack([L.x, L.y, L.z], 1).astype(np.float64)
+        for T in poses:
+            X = P @ T[:9].reshape(3, 3).T + T[9:]
+            u = L.K[0] * X[:, 0] / X[:, 2] + L.K[2]
+            v = L.K[1] * X[:, 1] / X[:, 2] + L.K[3]
+            keep &= (X[:, 2] > 1.0) & (u >= margin) & (u <= L.W - 1 - margin) & (v >= margin) & (v <= L.H - 1 - margin)
+    assert keep.sum() >= N // 2
+    for L in f.levels:
+        L.x, L.y, L.z, L.ref = L.x[keep], L.y[keep], L.z[keep], L.ref[keep]
+        if loss is not None:
+            L.loss = (loss, L.loss[1])
+    return f
+
+
+def _pix(L, T):
+    P = np.stack([L.x, L.y, L.z], 1).astype(np.float64)
+    X = P @ T[:9].reshape(3, 3).T + T[9:]
+    return L.K[0] * X[:, 0] / X[:, 2] + L.K[2], L.K[1] * X[:, 1] / X[:, 2] + L.K[3]
+
+
+def _close(a, b, rtol):
+    Ha, ga, ca, na = a
+    Hb, gb, cb, nb = b
+    assert na == nb
+    assert np.linalg.norm(Ha - Hb) <= rtol * np.linalg.norm(Hb)
+    assert np.linalg.norm(ga - gb) <= rtol * np.linalg.norm(gb)
+    assert abs(ca - cb) <= rtol * abs(cb)
+
+
+@pytest.mark.parametrize("loss", [0, 1])
+def test_constant_query_confidence_equals_scaled_anchor_weights(loss):
+    """W of Eq. (8) multiplies the anchor weight by the query confidence at
+    the projection: a constant confidence map kappa gives exactly the system
+    of the same frame with every anchor weight scaled by kappa."""
+    rng = np.random.default_rng(21)
+    base = small_frame(seed=13, N=120, M=1)
+    poses = [left_perturb(base.gt_pose, np.concatenate([rng.normal(0, 1.0, 3), rng.normal(0, 0.01, 3)]))
+             for _ in range(3)]
+    kappa = 0.37
+    a = _in_view_frame(13, poses, loss=loss)
+    b = _in_view_frame(13, poses, loss=loss)
+    for La, Lb in zip(a.levels, b.levels):
+        La.qconf = np.full((La.H, La.W), kappa)
+        Lb.ref_w = np.full(len(Lb.x), kappa)
+    oa, ob = oracle.OracleFrame(a), oracle.OracleFrame(b)
+    for l in range(2):
+        for T in poses:
+            _close(oracle.linearize(oa, l, T), oracle.linearize(ob, l, T), 1e-12)
+
+
+@pytest.mark.parametrize("loss", [0, 1])
+def test_affine_query_confidence_is_read_at_the_projection(loss):
+    """Bilinear interpolation reproduces an affine confidence field exactly,
+    so q(u, v) = q0 + qu u + qv v must equal anchor weights set to that
+    affine value at each anchor's projection (computed here with numpy).
+    Different slopes along u and v expose a transposed lookup."""
+    rng = np.random.default_rng(22)
+    base = small_frame(seed=14, N=120, M=1)
+    poses = [left_perturb(base.gt_pose, np.concatenate([rng.normal(0, 1.0, 3), rng.normal(0, 0.01, 3)]))
+             for _ in range(2)]
+    for T in poses:
+        a = _in_view_frame(14, [T], loss=loss)
+        b = _in_view_frame(14, [T], loss=loss)
+        for La, Lb in zip(a.levels, b.levels):
+            q0, qu, qv = 0.3, 0.7 / La.W, -0.2 / La.H       # positive over the map
+            vv, uu = np.mgrid[0:La.H, 0:La.W]
+            La.qconf = q0 + qu * uu + qv * vv
+            u, v = _pix(Lb, T)
+            Lb.ref_w = q0 + qu * u + qv * v
+        oa, ob = oracle.OracleFrame(a), oracle.OracleFrame(b)
+        for l in range(2):
+            _close(oracle.linearize(oa, l, T), oracle.linearize(ob, l, T), 1e-11)
+
+
+@pytest.mark.parametrize("loss", [0, 1, 2])
+def test_confidence_weight_sits_inside_the_robust_loss(loss):
+    """Eq. (2) applies rho to w |r|^2.  For the Cauchy and Huber losses
+    rho_b(kappa s) = kappa rho_{b / kappa}(s) (and rho'_b(kappa s) kappa =
+    kappa rho'_{b / kappa}(s)), so weights kappa at scale b give kappa times
+    the visual system of unit weights at scale b / kappa -- out-of-view
+    penalties included.  A weight applied outside rho breaks this."""
+    rng = np.random.default_rng(23)
+    f = small_frame(seed=15, N=96, M=1)
+    f.use_gravity = f.use_range = 0
+    # a pose that leaves about 40 % of the anchors out of view
+    T = left_perturb(f.gt_pose, np.concatenate([rng.normal(0, 3.0, 3), rng.normal(0, 0.2, 3)]))
+    kappa = 4.5
+    a = small_frame(seed=15, N=96, M=1)
+    b = small_frame(seed=15, N=96, M=1)
+    for fr in (a, b):
+        fr.use_gravity = fr.use_range = 0
+    for La, Lb in zip(a.levels, b.levels):
+        scale = La.loss[1]
+        La.loss = (loss, scale)
+        La.ref_w = np.full(len(La.x), kappa)
+        Lb.loss = (loss, scale / kappa)
+    oa, ob = oracle.OracleFrame(a), oracle.OracleFrame(b)
+    for l in range(2):
+        Ha, ga, ca, na = oracle.linearize_visual(oa, l, T)
+        Hb, gb, cb, nb = oracle.linearize_visual(ob, l, T)
+        assert na == nb and 0 < na < 96               # both visible anchors and penalties
+        _close((Ha, ga, ca, na), (kappa * Hb, kappa * gb, kappa * cb, nb), 1e-12)
+
+
 # ---------------------------------------------------------------- Jacobians
 def fd_jacobian(fun, T, h=1e-6):
     cols = []
