@@ -6,10 +6,11 @@
 namespace pilot {
 
 struct TileConfig {
-    int G;          // lanes per anchor = hypotheses per tile (4, 8 or 16)
-    int PPG;        // anchors per lane group per work item
-    int grid;       // blocks per CU of a persistent grid (0: one block per item); launch: blocks
-    int variant = 1;    // 1: batch-then-compute loop; 2: software-pipelined loop
+    int G = 4;          // lanes per anchor = hypotheses per tile (4, 8 or 16)
+    int PPG = 1;        // anchors per lane group per work item
+    int grid = 0;       // blocks per CU of a persistent grid (0: one block per item); launch: blocks
+    int variant = 1;    // pass kernel: 1 batch-then-compute loop, 2 software-pipelined loop,
+                        // 3-8 per-cell Gram tables (see pilot_pass3.inc)
 };
 
 // True if a pass kernel exists for (C, dtype, G).
@@ -33,9 +34,14 @@ hipError_t launch_init(const FrameDev *frames, int n_frames, int max_M, HypState
                        int diag_level, hipStream_t s, int *flags = nullptr, int n_flags = 0,
                        int flag_stride = 1);
 
-// Per-cell Gram matrices of the bilinear coefficients of a feature map
-// (pass kernel variants 3 to 8): 10 doubles per cell, cells y0 W + x0.
-hipError_t launch_gram(const void *feat, int H, int W, int C, int dtype, double *gram, hipStream_t s);
+// Per-cell Gram matrices of the bilinear coefficients of the feature map of
+// level `level` of frames[frame] (pass kernel variants 3 to 8): 10 doubles
+// per cell, cells y0 W + x0, written to that level's `gram`.  The kernel
+// reads the map, its shape and the table pointer from the device descriptor;
+// H, W, C and dtype (the host's copy of them) size the grid and pick the
+// instantiation.
+hipError_t launch_gram(const FrameDev *frames, int frame, int level, int H, int W, int C, int dtype,
+                       hipStream_t s);
 
 // Geo-anchor lift and reference-descriptor sampling (see pilot_lift).
 hipError_t launch_lift(const float *dsm, int Hd, int Wd, double x0, double y0, double gsd, const float *uv, int N,

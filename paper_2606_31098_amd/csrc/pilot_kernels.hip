@@ -491,9 +491,16 @@ __device__ __forceinline__ double quad_sum(double v)
 // dealt to the 8 XCDs round-robin; the block index is remapped so that each
 // XCD walks one contiguous band of cell rows, and the map row shared by two
 // consecutive cell rows is read into one XCD's L2 rather than two.
+// The map, its shape and the table are read from the frame descriptor in
+// device memory (not passed by value), so a captured graph replayed for a new
+// frame of the same shape builds the new frame's tables.
 template <int DT>
-__global__ __launch_bounds__(256) void gram_kernel(const void *feat, int H, int W, int C, double *gram)
+__global__ __launch_bounds__(256) void gram_kernel(const FrameDev *frames, int fi, int level)
 {
+    const LevelDev &L = frames[fi].lv[level];
+    const void *feat = L.feat;
+    const int H = L.H, W = L.W, C = L.C;
+    double *gram = const_cast<double *>(L.gram);
     const unsigned nb = gridDim.x, xcd = blockIdx.x % 8u, per = nb / 8u, rem = nb % 8u;
     const unsigned lb = xcd * per + min(xcd, rem) + blockIdx.x / 8u;
     const long cell = ((long)lb * blockDim.x + threadIdx.x) >> 2;
@@ -537,15 +544,15 @@ __global__ __launch_bounds__(256) void gram_kernel(const void *feat, int H, int 
     }
 }
 
-hipError_t launch_gram(const void *feat, int H, int W, int C, int dtype, double *gram, hipStream_t s)
+hipError_t launch_gram(const FrameDev *frames, int frame, int level, int H, int W, int C, int dtype, hipStream_t s)
 {
     const long cells = (long)H * W;
     if (cells <= 0 || C % 16) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((4 * cells + 255) / 256)), block(256);
     if (dtype == 0)
-        hipLaunchKernelGGL(gram_kernel<0>, grid, block, 0, s, feat, H, W, C, gram);
+        hipLaunchKernelGGL(gram_kernel<0>, grid, block, 0, s, frames, frame, level);
     else
-        hipLaunchKernelGGL(gram_kernel<1>, grid, block, 0, s, feat, H, W, C, gram);
+        hipLaunchKernelGGL(gram_kernel<1>, grid, block, 0, s, frames, frame, level);
     return hipGetLastError();
 }
 

@@ -47,7 +47,7 @@ struct DevBuf {
 
 struct LaunchGroup {
     int level, C, dtype;
-    TileConfig tc;
+    TileConfig tc{};
     int item_off, n_items;
     int tile_off, n_tiles;
     int passes;
@@ -83,7 +83,7 @@ struct ServingSlot {
     int hyp_base = 0;
     size_t bytes = 0;
     uint64_t admit_step = 0;
-    pilot_frame frame;
+    pilot_frame frame{};
     FrameDev dev{};      // host copy of the slot's device descriptor
     DevBuf gram;         // Gram tables of the slot's Gram-variant levels (kept for reuse)
 };
@@ -360,7 +360,7 @@ std::string tune_key(int C, int dtype, int N, int M, long HW)
 
 TileConfig heuristic_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M, long HW)
 {
-    TileConfig tc;
+    TileConfig tc{};
     tc.G = (C >= 128) ? 8 : 4;      // measured: G = 4 up to C = 64, G = 8 at C = 128
     const int NG = kBlock / tc.G;
     const long ht = (M + tc.G - 1) / tc.G;
@@ -517,7 +517,7 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
                 by_class[{L.C, L.dtype, tc.G, tc.PPG, tc.variant}].push_back(i);
             }
         for (auto &kv : by_class) {
-            LaunchGroup g;
+            LaunchGroup g{};
             g.level = l;
             g.C = kv.first[0];
             g.dtype = kv.first[1];
@@ -549,6 +549,8 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
                     const pilot_level &Li = frames[i].level[l];
                     plan.gram_jobs.push_back(Plan::GramJob{i, l, plan.gram_bytes});
                     plan.gram_bytes += ((size_t)Li.H * Li.W * 10 * sizeof(double) + 255) & ~(size_t)255;
+                    // a captured graph bakes in each Gram launch's grid and instantiation
+                    key << "|g" << i << "." << l << ":" << Li.H << "x" << Li.W << "x" << Li.C << "d" << Li.dtype;
                 }
             plan.partial_floats = std::max(plan.partial_floats, (size_t)g.n_items * g.tc.G * kNV);
             plan.groups.push_back(g);
@@ -642,7 +644,7 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Laun
         for (int t = g.tile_off; t < g.tile_off + g.n_tiles; ++t)
             if (!plan.frames[plan.tiles[t].frame].lv[g.level].gram)
                 return fail(ctx, PILOT_EDEVICE, "internal: Gram pass variant without a Gram table (level %d)", g.level);
-    PassArgs a;
+    PassArgs a{};
     a.frames = dp.frames;
     a.items = dp.items + g.item_off;
     a.n_items = g.n_items;
@@ -665,7 +667,7 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Laun
         HIPCHK(ctx, hipEventRecord(tl.b, s));
         ctx->timed.push_back(tl);
     }
-    EpilogueArgs e;
+    EpilogueArgs e{};
     e.frames = dp.frames;
     e.tiles = dp.tiles + g.tile_off;
     e.n_tiles = g.n_tiles;
@@ -685,12 +687,13 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Laun
 }
 
 // Gram tables of the plan's Gram-variant levels (they depend on the feature
-// maps only, and are rebuilt with every solve since a replay may see new maps).
-int enqueue_gram(pilot_ctx *ctx, const Plan &plan, hipStream_t s)
+// maps only, and are rebuilt with every solve since a replay may see new maps:
+// the kernel reads each map's address from the device descriptors).
+int enqueue_gram(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, hipStream_t s)
 {
     for (const Plan::GramJob &j : plan.gram_jobs) {
         const LevelDev &L = plan.frames[j.frame].lv[j.level];
-        HIPCHK(ctx, launch_gram(L.feat, L.H, L.W, L.C, L.dtype, (double *)L.gram, s));
+        HIPCHK(ctx, launch_gram(dp.frames, j.frame, j.level, L.H, L.W, L.C, L.dtype, s));
     }
     return PILOT_OK;
 }
@@ -698,7 +701,7 @@ int enqueue_gram(pilot_ctx *ctx, const Plan &plan, hipStream_t s)
 // The full LM schedule of a plan on stream s.
 int enqueue_schedule(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, hipStream_t s, bool timed)
 {
-    if (int rc = enqueue_gram(ctx, plan, s)) return rc;
+    if (int rc = enqueue_gram(ctx, plan, dp, s)) return rc;
     HIPCHK(ctx, launch_init(dp.frames, (int)plan.frames.size(), plan.max_M, (HypState *)ctx->hs.p,
                             (PoseEval *)ctx->pose.p, (int *)ctx->hlev.p, MODE_LM, nullptr, 0, s,
                             (int *)ctx->passflag.p, PILOT_MAX_LEVELS * plan.flag_stride, plan.flag_stride));
@@ -730,7 +733,7 @@ void load_tune_cache(pilot_ctx *ctx)
     if (ctx->tune_cache.empty()) return;
     std::ifstream in(ctx->tune_cache);
     std::string key;
-    TileConfig tc;
+    TileConfig tc{};
     while (in >> key >> tc.G >> tc.PPG >> tc.grid >> tc.variant)
         if (pass_supported(16, 0, tc.G) && tc.PPG >= 1 && tc.PPG <= 64 && tc.variant >= 1 && tc.variant <= 8)
             ctx->tuned[key] = tc;
@@ -936,7 +939,7 @@ int pilot_linearize(pilot_ctx *ctx, const pilot_frame *frame, int level, const d
     if ((rc = ensure_state(ctx, plan))) return rc;
     DevPtrs dp;
     if ((rc = upload_plan(ctx, plan, dp))) return rc;
-    if ((rc = enqueue_gram(ctx, plan, ctx->stream))) return rc;
+    if ((rc = enqueue_gram(ctx, plan, dp, ctx->stream))) return rc;
     HIPCHK(ctx, launch_init(dp.frames, 1, plan.max_M, (HypState *)ctx->hs.p, (PoseEval *)ctx->pose.p,
                             (int *)ctx->hlev.p, MODE_DIAG, poses, level, ctx->stream));
     for (const LaunchGroup &g : plan.groups)
@@ -1266,7 +1269,7 @@ int serving_rebuild(pilot_ctx *ctx)
                 by_class[{L.C, L.dtype, tc.G, tc.PPG, tc.variant}].push_back(k);
             }
         for (auto &kv : by_class) {
-            LaunchGroup g;
+            LaunchGroup g{};
             g.level = l;
             g.C = kv.first[0];
             g.dtype = kv.first[1];
@@ -1351,7 +1354,7 @@ int pilot_admit(pilot_ctx *ctx, const pilot_frame *frame, const pilot_result *re
     const int base = arena_alloc(ctx, frame->M);
     if (base < 0) return fail(ctx, PILOT_EAGAIN, "hypothesis arena full (%d hypotheses)", ctx->arena_cap);
 
-    FrameDev d;
+    FrameDev d{};
     fill_frame_dev(d, *frame, result, base);
     d.slot = s;
     d.done_flag = (int *)ctx->s_done.p + s;
@@ -1391,7 +1394,7 @@ int pilot_admit(pilot_ctx *ctx, const pilot_frame *frame, const pilot_result *re
     for (int l = 0; l < frame->n_levels; ++l)
         if (gneed[l]) {
             const pilot_level &L = frame->level[l];
-            HIPCHK(ctx, launch_gram(L.feat, L.H, L.W, L.C, L.dtype, (double *)d.lv[l].gram, ctx->stream));
+            HIPCHK(ctx, launch_gram(dst, 0, l, L.H, L.W, L.C, L.dtype, ctx->stream));
         }
     sl.dev = d;
     sl.active = true;
@@ -1468,9 +1471,17 @@ int pilot_poll(pilot_ctx *ctx, int slot)
             return fail(ctx, PILOT_EDEVICE, "hipEventQuery: %s", hipGetErrorString(q));
     }
     if (!best || !best->host[slot]) return 0;
+    // The slot's device descriptor is cleared (M = 0) behind the steps already
+    // enqueued: the prune and finalize kernels of later steps walk every slot,
+    // and a stale descriptor would rank or write the hypotheses of whichever
+    // frame is given this slot's hypothesis range next.
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipMemsetAsync((FrameDev *)ctx->s_frames.p + slot, 0, sizeof(FrameDev), ctx->stream));
     arena_release(ctx, sl.hyp_base, sl.M);
     ctx->serv_bytes -= sl.bytes;
+    DevBuf gram = sl.gram;                // the slot keeps its Gram-table buffer for the next frame
     sl = ServingSlot();
+    sl.gram = gram;
     ctx->serv_dirty = true;
     return 1;
 }

@@ -401,3 +401,32 @@ def test_serving_with_gram_tables_matches_solves(alone, tmp_path):
     torch.cuda.synchronize()
     for i in range(len(dfs)):
         assert same(as_np(results[i]), ref[i]), i
+
+
+def test_graph_replay_reads_the_new_frames_maps(tmp_path):
+    """One context solves frame A, then frame B of the same shapes (other
+    seed, other device buffers): the captured graph is replayed for B, and its
+    Gram tables must be built from B's maps, not A's.  B's results equal a
+    solve without graphs, bitwise."""
+    from paper_2606_31098_amd import _abi as A
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    fa, fb = small(81), small(82)
+    cache = tmp_path / "tiles.txt"
+    with open(cache, "w") as fh:
+        for L in fa.levels:
+            fh.write(f"C{L.C}_d0_N{int(math.floor(math.log2(L.N)))}_M{int(math.floor(math.log2(fa.M)))}"
+                     f"_P{int(math.floor(math.log2(L.H * L.W)))}_v3 4 2 0 3\n")
+    g = Context(0, tune_cache=str(cache))
+    e = Context(0, flags=A.FLAG_NO_GRAPH, tune_cache=str(cache))
+    da, db = DeviceFrame(fa), DeviceFrame(fb)
+    say("graph: frame A, then frame B of the same shapes")
+    ra = as_np(g.solve([da])[0])
+    rb = as_np(g.solve([db])[0])
+    st = g.stats()
+    assert st.graph_captures == 1 and st.graph_replays == 2
+    eb = as_np(e.solve([db])[0])
+    ea = as_np(e.solve([da])[0])
+    torch.cuda.synchronize()
+    assert same(ra, ea)
+    assert same(rb, eb)
+    assert not same(ra, rb)
