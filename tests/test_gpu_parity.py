@@ -331,3 +331,85 @@ def test_range_gate_with_a_corrupted_reading_matches_oracle(ctx):
     assert b[0, 1] < 0.01 * f.lambda_range
     te, _ = S.pose_errors(gpu["poses"][0], f.gt_pose)
     assert te[0] < 0.5
+
+
+# --------------------------------------------------------------------------- photo losses
+@pytest.mark.parametrize("loss", [S.LOSS_HUBER, S.LOSS_L2])
+def test_photo_loss_kinds_match_oracle(ctx, loss):
+    """The Huber loss of Eq. (2) (and plain least squares) on the photometric
+    term: normal equations and cost at every level against the oracle, then a
+    full solve."""
+    from paper_2606_31098_amd.pilot import DeviceFrame
+    f = pyramid_frame(seed=12, N=1200, M=11)
+    for L in f.levels:
+        L.loss = (loss, L.loss[1])
+    rng = np.random.default_rng(12)
+    poses = np.stack([oracle.compose(oracle.se3_exp(np.concatenate([rng.normal(0, 2, 3), rng.normal(0, 0.02, 3)])),
+                                     f.gt_pose) for _ in range(f.M)])
+    fm = mask_edges(pyramid_frame(seed=12, N=1200, M=11), poses)
+    for L in fm.levels:
+        L.loss = (loss, L.loss[1])
+    df = DeviceFrame(fm)
+    of = oracle.OracleFrame(fm)
+    for lvl in range(len(fm.levels)):
+        say(f"linearize loss={loss} level={lvl}")
+        H21, g, cost, n = ctx.linearize(df, lvl, torch.as_tensor(poses, device="cuda"))
+        torch.cuda.synchronize()
+        H = unpack_h21(H21.cpu().numpy())
+        g, cost = g.cpu().numpy(), cost.cpu().numpy()
+        for m in range(f.M):
+            Ho, go, co, no = oracle.linearize(of, lvl, poses[m])
+            err = rel_frobenius(np.concatenate([H[m], g[m][:, None]], 1), np.concatenate([Ho, go[:, None]], 1))
+            assert err <= NEQ_TOL, (lvl, m, err)
+            assert abs(cost[m] - co) <= 1e-9 * abs(co), (lvl, m, cost[m], co)
+    say(f"solve loss={loss}")
+    gpu = solve_gpu(ctx, f)
+    orc = oracle.solve(f, threads=8)
+    rows, fails = compare_solutions(f, gpu, orc, POSE_TOL_M, POSE_TOL_DEG, f"loss{loss}")
+    assert not fails, fails
+    assert check_best(f, gpu, orc, POSE_TOL_M, POSE_TOL_DEG)
+
+
+# --------------------------------------------------------------------------- full-size levels
+@pytest.mark.parametrize("C,dtype,variant", [(128, "f32", 3), (128, "f32", 4), (128, "bf16", 6), (128, "bf16", 5),
+                                             (256, "f32", 3), (256, "bf16", 6)])
+def test_full_480x640_level_normal_equations_match_oracle(tmp_path, C, dtype, variant):
+    """The finest level at its benchmark size (480 x 640, N = 8192 anchors)
+    with the wide-channel pass kernels, element by element against the oracle
+    for 16 hypotheses (two tiles of G = 8), at the kernel variants the tile
+    database uses at these shapes."""
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    d = 0 if dtype == "f32" else 1
+    fp32_dots = variant in (5, 6, 8) and dtype == "bf16"
+    neq_tol, cost_tol = (1e-4, 1e-5) if fp32_dots else (NEQ_TOL, 1e-9)
+    say(f"full level C={C} dtype={dtype} variant={variant}: generating")
+    f = S.make_frame(2, 0, N=8192, M=16, level_shapes=((480, 640, C),), iters=(4,), dsm_side=256, seed=61)
+    if dtype == "bf16":
+        f = bf16_copy(f)
+    rng = np.random.default_rng(61)
+    # eight hypotheses near the truth (shared cells at this level) and eight farther off
+    poses = np.stack([oracle.compose(oracle.se3_exp(np.concatenate([rng.normal(0, s, 3), rng.normal(0, s / 100, 3)])),
+                                     f.gt_pose) for s in [0.3] * 8 + [3.0] * 8])
+    mask_edges(f, poses)
+    cache = tmp_path / "tune.txt"
+    L = f.levels[0]
+    cache.write_text(f"C{C}_d{d}_N{_floor_log2(L.N)}_M{_floor_log2(f.M)}_P{_floor_log2(L.H * L.W)}_v3 8 4 0 {variant}\n")
+    c = Context(0, tune_cache=str(cache))
+    assert f"V={variant}" in c.tile_choice(C, d, L.N, f.M, L.H * L.W)
+    df = DeviceFrame(f, dtype=dtype)
+    say(f"full level C={C} dtype={dtype} variant={variant}: linearize")
+    H21, g, cost, n = c.linearize(df, 0, torch.as_tensor(poses, device="cuda"))
+    torch.cuda.synchronize()
+    H = unpack_h21(H21.cpu().numpy())
+    g, cost, n = g.cpu().numpy(), cost.cpu().numpy(), n.cpu().numpy()
+    of = oracle.OracleFrame(f)
+    worst = 0.0
+    for m in range(f.M):
+        Ho, go, co, no = oracle.linearize(of, 0, poses[m])
+        err = rel_frobenius(np.concatenate([H[m], g[m][:, None]], 1), np.concatenate([Ho, go[:, None]], 1))
+        worst = max(worst, err)
+        assert err <= neq_tol, (m, err)
+        assert abs(cost[m] - co) <= cost_tol * abs(co), (m, (cost[m] - co) / co)
+        assert abs(int(n[m]) - no) <= border_count(L, poses[m]), (m, n[m], no)
+    say(f"worst relative Frobenius error {worst:.2e}")
+    c.close()
