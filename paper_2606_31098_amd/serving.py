@@ -74,11 +74,17 @@ class ServingLoop:
         prev: Dict[int, Any] = {}
         active: Dict[int, tuple] = {}
         t0 = self.clock()
+        skipped = [0.0]                                  # idle time jumped over (realtime=False)
+
+        def elapsed():
+            return self.clock() - t0 + skipped[0]
         nxt = 0
         while nxt < len(reqs) or any(queues.values()) or active:
-            now = self.clock() - t0
-            if not realtime and not active and not any(queues.values()) and nxt < len(reqs):
-                now = max(now, reqs[nxt].t_arrival)      # skip idle time
+            now = elapsed()
+            if not realtime and not active and not any(queues.values()) and nxt < len(reqs) \
+                    and reqs[nxt].t_arrival > now:
+                skipped[0] += reqs[nxt].t_arrival - now  # skip idle time: the clock jumps to the arrival
+                now = elapsed()
             while nxt < len(reqs) and reqs[nxt].t_arrival <= now:
                 queues[reqs[nxt].stream].append(reqs[nxt])
                 nxt += 1
@@ -98,7 +104,7 @@ class ServingLoop:
                     break                               # no slot or budget: retry after the next pass
                 queues[s].popleft()
                 busy[s] = True
-                active[slot] = (req, df, res, keep, self.clock() - t0, st.steps)
+                active[slot] = (req, df, res, keep, elapsed(), st.steps)
             st.max_active = max(st.max_active, len(active))
             if active:
                 t1 = self.clock()
@@ -106,13 +112,13 @@ class ServingLoop:
                 st.host_step += self.clock() - t1
                 st.steps += 1
             elif nxt < len(reqs) and realtime:
-                time.sleep(max(0.0, min(reqs[nxt].t_arrival - (self.clock() - t0), 0.002)))
+                time.sleep(max(0.0, min(reqs[nxt].t_arrival - elapsed(), 0.002)))
             t1 = self.clock()
             done = [slot for slot in list(active) if self.ctx.poll(slot)]
             st.host_poll += self.clock() - t1
             for slot in done:
                 req, df, res, keep, t_adm, s0 = active.pop(slot)
-                c = Completion(req, t_adm, self.clock() - t0, res, st.steps - s0)
+                c = Completion(req, t_adm, elapsed(), res, st.steps - s0)
                 st.completions.append(c)
                 busy[req.stream] = False
                 prev[req.stream] = res
@@ -120,8 +126,6 @@ class ServingLoop:
                     on_complete(c)
             if not active and not any(queues.values()) and nxt >= len(reqs):
                 break
-            if active and not realtime:
-                pass
         self.ctx.sync()
-        st.wall = self.clock() - t0
+        st.wall = elapsed()
         return st
