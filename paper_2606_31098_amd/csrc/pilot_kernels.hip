@@ -245,7 +245,8 @@ __global__ __launch_bounds__(256) void init_kernel(const FrameDev *frames, HypSt
     if (mode == MODE_DIAG) {
         for (int i = 0; i < 12; ++i) src[i] = dposes[(size_t)12 * m + i];
     } else if (f.hyp_offsets) {
-        // hypothesis m around the prior: centre += (dx, dy, 0), R_wc <- Rz(dyaw) R_wc,
+        // hypothesis m around the prior: centre += (dx, dy, 0), R_wc <- Rz(dyaw) R_wc
+        // (a positive dyaw turns the camera counter-clockwise seen from above),
         // i.e. R <- R Rz(-dyaw), t <- -R C
         const int b = f.prior_best ? max(*f.prior_best, 0) : 0;
         const double *T = f.prior_poses + (size_t)12 * b;
@@ -258,8 +259,8 @@ __global__ __launch_bounds__(256) void init_kernel(const FrameDev *frames, HypSt
         sincos(dz, &sz, &cz);
         for (int r = 0; r < 3; ++r) {
             const double a0 = T[3 * r], a1 = T[3 * r + 1];
-            src[3 * r] = a0 * cz + a1 * sz;           // R Rz(-dyaw): columns 0, 1 rotate
-            src[3 * r + 1] = -a0 * sz + a1 * cz;
+            src[3 * r] = a0 * cz - a1 * sz;           // R Rz(-dyaw): columns 0, 1 rotate
+            src[3 * r + 1] = a0 * sz + a1 * cz;
             src[3 * r + 2] = T[3 * r + 2];
         }
         for (int r = 0; r < 3; ++r) src[9 + r] = -(src[3 * r] * Cw[0] + src[3 * r + 1] * Cw[1] + src[3 * r + 2] * Cw[2]);

@@ -200,6 +200,27 @@ def test_device_hypotheses_from_prior():
         assert dt[0] < POSE_TOL_M and dr[0] < POSE_TOL_DEG, (m, dt, dr)
 
 
+def test_device_hypotheses_follow_the_offsets_convention():
+    """Device generation of hypotheses far from the prior (20 m, 10 deg) and
+    one LM iteration per level, so that the results still depend on where
+    each hypothesis started: they match the same solve from host-generated
+    poses (centre += (dx, dy), R_wc <- Rz(dyaw) R_wc).  A sign or axis slip
+    in the generator moves them by metres."""
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    f = small(32, M=16, iters=(1, 1, 1))
+    rng = np.random.default_rng(9)
+    offs = np.stack([rng.uniform(-20, 20, 16), rng.uniform(-20, 20, 16), np.radians(rng.uniform(-10, 10, 16))], 1)
+    prior = f.meta["init_pose"]
+    host_poses = np.stack([S.hypothesis(prior, *o) for o in offs])
+    ctx = Context(0)
+    a = as_np(ctx.solve([DeviceFrame(f, poses=host_poses)])[0])
+    b = as_np(ctx.solve([DeviceFrame(f, prior=torch.as_tensor(prior[None]), hyp_offsets=offs)])[0])
+    torch.cuda.synchronize()
+    for m in range(16):
+        dt, dr = S.pose_errors(a["poses"][m], b["poses"][m])
+        assert dt[0] < 1e-5 and dr[0] < 1e-6, (m, dt, dr)
+
+
 def test_abi_errors_launch_nothing(alone):
     from paper_2606_31098_amd import _abi as A
     from paper_2606_31098_amd.pilot import Context, DeviceFrame, DeviceResult, PilotError
