@@ -219,6 +219,26 @@ const char *pilot_last_error(const pilot_ctx *ctx);
 int pilot_solve(pilot_ctx *ctx, const pilot_frame *frames, int n_frames,
                 const pilot_result *results);
 
+/* pilot_solve for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, hosts that forbid hipMalloc): the
+ * same schedule and kernels, with every piece of workspace (descriptors,
+ * Gram tables, LM states, partial sums, pass flags) carved from one fixed
+ * device array of PILOT_STATIC_SCRATCH_BYTES per GPU that the library holds
+ * from the first pilot_create on that GPU until the process ends.  Calls no
+ * hipMalloc, hipFree, pinned-memory allocation or graph instantiation: the
+ * descriptors are copied from host memory the context keeps.  Tiles come
+ * from the context's tile database or the built-in heuristic (no autotuning,
+ * whatever the flags), so with the same tiles the results equal pilot_solve's
+ * bit for bit.  Frames whose workspace exceeds the scratch are refused with
+ * PILOT_ENOMEM before anything is enqueued (the message gives the bytes
+ * needed).  Every call on one GPU, from any context, uses that GPU's single
+ * array and leaves its contents behind: calls whose work can overlap on one GPU
+ * (contexts on different streams without an ordering between them) race and
+ * give undefined results; calls ordered on one stream are safe. */
+#define PILOT_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int pilot_solve_static(pilot_ctx *ctx, const pilot_frame *frames, int n_frames,
+                       const pilot_result *results);
+
 /* Diagnostic: the damped system's terms at given poses, without an LM step.
  * For level `level` of `frame` and poses (device, frame->M*12): H21 (device,
  * M*21, upper triangle of the 6x6 row by row), g6 (M*6), cost (M), nvalid

@@ -71,7 +71,7 @@ class Stats(C.Structure):
 EXPORTS = ["pilot_create", "pilot_destroy", "pilot_last_error", "pilot_solve", "pilot_linearize",
            "pilot_admit_cost", "pilot_admit", "pilot_step", "pilot_poll", "pilot_serving_state",
            "pilot_get_stats", "pilot_autotune", "pilot_tile_choice", "pilot_abi_version", "pilot_sizeof",
-           "pilot_sync", "pilot_lift"]
+           "pilot_sync", "pilot_lift", "pilot_solve_static"]
 
 _lib = None
 
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH):
     L.pilot_last_error.argtypes = [_vp]
     L.pilot_last_error.restype = C.c_char_p
     L.pilot_solve.argtypes = [_vp, P(Frame), C.c_int, P(Result)]
+    L.pilot_solve_static.argtypes = [_vp, P(Frame), C.c_int, P(Result)]
     L.pilot_linearize.argtypes = [_vp, P(Frame), C.c_int, _vp, _vp, _vp, _vp, _vp]
     L.pilot_admit_cost.argtypes = [_vp, P(Frame), P(C.c_size_t)]
     L.pilot_admit.argtypes = [_vp, P(Frame), P(Result), P(C.c_int)]

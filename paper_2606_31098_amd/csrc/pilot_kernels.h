@@ -58,3 +58,18 @@ hipError_t launch_finalize(const FrameDev *frames, int n_frames, const HypState 
                            const int *hlev, hipStream_t s);
 
 }  // namespace pilot
+
+namespace pilot {
+
+// The fixed device scratch of pilot_solve_static (pilot_static.hip):
+// its size in bytes, the per-device set-up that takes the array's device
+// address (call with `device` current), and that address (NULL before the
+// set-up on that device).
+size_t static_scratch_bytes();
+hipError_t static_scratch_init(int device);
+void *static_scratch(int device);
+
+// Zero n_words 32-bit words on stream s with a fill kernel.
+hipError_t launch_zero_words(void *p, int n_words, hipStream_t s);
+
+}  // namespace pilot

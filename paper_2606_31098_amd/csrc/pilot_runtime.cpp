@@ -111,6 +111,8 @@ struct pilot_ctx {
     // it was made in: a solve whose descriptors are the same skips the copy
     std::vector<char> desc_img, desc_next;
     unsigned desc_gen = ~0u;
+    // host image of the descriptors of the last pilot_solve_static call
+    std::vector<char> static_img;
 
     // pinned staging ring
     struct Stage {
@@ -579,6 +581,29 @@ struct DevPtrs {
     TileItem *tiles;
 };
 
+// Device workspace a schedule runs on: the context's buffers, or the fixed
+// scratch of pilot_solve_static.
+struct Ws {
+    HypState *hs = nullptr;
+    PoseEval *pose = nullptr;
+    int *hlev = nullptr;
+    float *partials = nullptr;
+    unsigned long long *pairs = nullptr;
+    int *passflag = nullptr;
+};
+
+Ws ws_of(const pilot_ctx *ctx)
+{
+    Ws w;
+    w.hs = (HypState *)ctx->hs.p;
+    w.pose = (PoseEval *)ctx->pose.p;
+    w.hlev = (int *)ctx->hlev.p;
+    w.partials = (float *)ctx->partials.p;
+    w.pairs = (unsigned long long *)ctx->pairs.p;
+    w.passflag = (int *)ctx->passflag.p;
+    return w;
+}
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Copy the plan's descriptors to the device (pinned staging, async).  The
@@ -636,7 +661,7 @@ int ensure_state(pilot_ctx *ctx, Plan &plan)
 }
 
 // Enqueue one pass (pass kernel + epilogue) of a launch group.
-int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const LaunchGroup &g, int mode,
+int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Ws &ws, const LaunchGroup &g, int mode,
                  hipStream_t s, bool timed, const int *run_flag = nullptr, int *next_flag = nullptr,
                  bool mask_first = false)
 {
@@ -649,9 +674,9 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Laun
     a.items = dp.items + g.item_off;
     a.n_items = g.n_items;
     a.level = g.level;
-    a.pose = (const PoseEval *)ctx->pose.p;
-    a.hlev = (const int *)ctx->hlev.p;
-    a.partials = (float *)ctx->partials.p;
+    a.pose = ws.pose;
+    a.hlev = ws.hlev;
+    a.partials = ws.partials;
     a.run_flag = run_flag;
     TimedLaunch tl{};
     if (timed) {
@@ -674,11 +699,11 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Laun
     e.level = g.level;
     e.G = g.tc.G;
     e.mode = mode;
-    e.partials = (const float *)ctx->partials.p;
-    e.pose = (PoseEval *)ctx->pose.p;
-    e.hlev = (int *)ctx->hlev.p;
-    e.hs = (HypState *)ctx->hs.p;
-    e.pairs = (unsigned long long *)ctx->pairs.p + g.stat_class;
+    e.partials = ws.partials;
+    e.pose = ws.pose;
+    e.hlev = ws.hlev;
+    e.hs = ws.hs;
+    e.pairs = ws.pairs + g.stat_class;
     e.next_flag = next_flag;
     e.mask_first = mask_first ? 1 : 0;
     HIPCHK(ctx, launch_epilogue(e, s));
@@ -699,12 +724,11 @@ int enqueue_gram(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, hipStream_
 }
 
 // The full LM schedule of a plan on stream s.
-int enqueue_schedule(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, hipStream_t s, bool timed)
+int enqueue_schedule(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Ws &ws, hipStream_t s, bool timed)
 {
     if (int rc = enqueue_gram(ctx, plan, dp, s)) return rc;
-    HIPCHK(ctx, launch_init(dp.frames, (int)plan.frames.size(), plan.max_M, (HypState *)ctx->hs.p,
-                            (PoseEval *)ctx->pose.p, (int *)ctx->hlev.p, MODE_LM, nullptr, 0, s,
-                            (int *)ctx->passflag.p, PILOT_MAX_LEVELS * plan.flag_stride, plan.flag_stride));
+    HIPCHK(ctx, launch_init(dp.frames, (int)plan.frames.size(), plan.max_M, ws.hs, ws.pose, ws.hlev, MODE_LM,
+                            nullptr, 0, s, ws.passflag, PILOT_MAX_LEVELS * plan.flag_stride, plan.flag_stride));
     for (int l = 0; l < plan.max_levels; ++l) {
         int maxp = 0;
         for (const LaunchGroup &g : plan.groups)
@@ -713,18 +737,16 @@ int enqueue_schedule(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, hipStr
             for (const LaunchGroup &g : plan.groups)
                 if (g.level == l && k < g.passes) {
                     // pass k of level l runs only if pass k - 1 left a hypothesis at level l
-                    int *flags = (int *)ctx->passflag.p + (size_t)l * plan.flag_stride;
-                    int rc = enqueue_pass(ctx, plan, dp, g, MODE_LM, s, timed, flags + k, flags + k + 1);
+                    int *flags = ws.passflag + (size_t)l * plan.flag_stride;
+                    int rc = enqueue_pass(ctx, plan, dp, ws, g, MODE_LM, s, timed, flags + k, flags + k + 1);
                     if (rc) return rc;
                 }
         bool prunes = false;
         for (const FrameDev &f : plan.frames) prunes = prunes || (f.keep_top > 0 && f.prune_level == l);
         if (prunes)
-            HIPCHK(ctx, launch_prune(dp.frames, (int)plan.frames.size(), (HypState *)ctx->hs.p, (PoseEval *)ctx->pose.p,
-                                     (int *)ctx->hlev.p, s));
+            HIPCHK(ctx, launch_prune(dp.frames, (int)plan.frames.size(), ws.hs, ws.pose, ws.hlev, s));
     }
-    HIPCHK(ctx, launch_finalize(dp.frames, (int)plan.frames.size(), (const HypState *)ctx->hs.p,
-                                (const int *)ctx->hlev.p, s));
+    HIPCHK(ctx, launch_finalize(dp.frames, (int)plan.frames.size(), ws.hs, ws.hlev, s));
     return PILOT_OK;
 }
 
@@ -810,6 +832,13 @@ int pilot_create(pilot_ctx **out, const pilot_config *cfg)
         pilot_destroy(ctx);
         return rc;
     }
+    // the fixed scratch of pilot_solve_static: its address on this device
+    e = static_scratch_init(cfg->device);
+    if (e != hipSuccess) {
+        int rc = fail(nullptr, PILOT_EDEVICE, "hipGetSymbolAddress(static scratch): %s", hipGetErrorString(e));
+        pilot_destroy(ctx);
+        return rc;
+    }
     load_tune_cache(ctx);
     *out = ctx;
     return PILOT_OK;
@@ -843,10 +872,13 @@ void pilot_destroy(pilot_ctx *ctx)
     delete ctx;
 }
 
-int pilot_solve(pilot_ctx *ctx, const pilot_frame *frames, int n_frames, const pilot_result *results)
+}  // extern "C"
+
+namespace {
+
+// Argument checks shared by pilot_solve and pilot_solve_static.
+int validate_solve(pilot_ctx *ctx, const pilot_frame *frames, int n_frames, const pilot_result *results)
 {
-    if (!ctx) return fail(nullptr, PILOT_EINVAL, "ctx: NULL");
-    ctx->err.clear();
     if (!frames) return fail(ctx, PILOT_EINVAL, "frames: NULL");
     if (n_frames < 1) return fail(ctx, PILOT_EINVAL, "n_frames: must be >= 1 (got %d)", n_frames);
     if (!results) return fail(ctx, PILOT_EINVAL, "results: NULL");
@@ -861,6 +893,18 @@ int pilot_solve(pilot_ctx *ctx, const pilot_frame *frames, int n_frames, const p
     }
     if (total > (1L << 24)) return fail(ctx, PILOT_EINVAL, "total hypotheses %ld exceed 2^24", total);
     if (ctx->n_active() > 0) return fail(ctx, PILOT_EINVAL, "context has active serving slots");
+    return PILOT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pilot_solve(pilot_ctx *ctx, const pilot_frame *frames, int n_frames, const pilot_result *results)
+{
+    if (!ctx) return fail(nullptr, PILOT_EINVAL, "ctx: NULL");
+    ctx->err.clear();
+    if (int rc = validate_solve(ctx, frames, n_frames, results)) return rc;
     HIPCHK(ctx, hipSetDevice(ctx->device));
 
     if (ctx->flags & PILOT_FLAG_AUTOTUNE) {
@@ -885,13 +929,13 @@ int pilot_solve(pilot_ctx *ctx, const pilot_frame *frames, int n_frames, const p
     if ((rc = upload_plan(ctx, plan, dp))) return rc;
 
     if (ctx->flags & PILOT_FLAG_NO_GRAPH)
-        return enqueue_schedule(ctx, plan, dp, ctx->stream, (ctx->flags & PILOT_FLAG_PROFILE) != 0);
+        return enqueue_schedule(ctx, plan, dp, ws_of(ctx), ctx->stream, (ctx->flags & PILOT_FLAG_PROFILE) != 0);
 
     std::string key = plan.key + "#" + std::to_string(ctx->generation) + "#" + std::to_string((uintptr_t)dp.frames);
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
         HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-        rc = enqueue_schedule(ctx, plan, dp, ctx->cap_stream, false);
+        rc = enqueue_schedule(ctx, plan, dp, ws_of(ctx), ctx->cap_stream, false);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
         if (rc) {
@@ -914,6 +958,69 @@ int pilot_solve(pilot_ctx *ctx, const pilot_frame *frames, int n_frames, const p
     HIPCHK(ctx, hipGraphLaunch(it->second, ctx->stream));
     ctx->graph_replays++;
     return PILOT_OK;
+}
+
+int pilot_solve_static(pilot_ctx *ctx, const pilot_frame *frames, int n_frames, const pilot_result *results)
+{
+    if (!ctx) return fail(nullptr, PILOT_EINVAL, "ctx: NULL");
+    ctx->err.clear();
+    if (int rc = validate_solve(ctx, frames, n_frames, results)) return rc;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    char *base = (char *)static_scratch(ctx->device);
+    if (!base) return fail(ctx, PILOT_EDEVICE, "internal: no static scratch address for device %d", ctx->device);
+
+    // tiles from the context's tile database or the heuristic (no tuning here)
+    Plan plan;
+    build_plan(ctx, frames, n_frames, results, -1, plan);
+    const size_t fb = align256(plan.frames.size() * sizeof(FrameDev));
+    const size_t ib = align256(std::max<size_t>(1, plan.items.size()) * sizeof(WorkItem));
+    const size_t tb = align256(std::max<size_t>(1, plan.tiles.size()) * sizeof(TileItem));
+    const size_t H = std::max(1, plan.total_hyps);
+    size_t off = fb + ib + tb;
+    const size_t o_gram = off;
+    off += align256(plan.gram_bytes);
+    const size_t o_hs = off;
+    off += align256(H * sizeof(HypState));
+    const size_t o_pose = off;
+    off += align256(H * sizeof(PoseEval));
+    const size_t o_hlev = off;
+    off += align256(H * sizeof(int));
+    const size_t o_part = off;
+    off += align256(std::max<size_t>(1, plan.partial_floats) * sizeof(float));
+    const size_t o_pairs = off;
+    off += align256(kStatClasses * sizeof(unsigned long long));
+    const size_t o_flag = off;
+    off += align256((size_t)PILOT_MAX_LEVELS * plan.flag_stride * sizeof(int));
+    if (off > static_scratch_bytes())
+        return fail(ctx, PILOT_ENOMEM,
+                    "pilot_solve_static: these frames need %zu bytes of device scratch; the fixed scratch holds %zu "
+                    "(use pilot_solve)", off, static_scratch_bytes());
+
+    for (const Plan::GramJob &j : plan.gram_jobs)
+        plan.frames[j.frame].lv[j.level].gram = (const double *)(base + o_gram + j.offset);
+    DevPtrs dp;
+    dp.frames = (FrameDev *)base;
+    dp.items = (WorkItem *)(base + fb);
+    dp.tiles = (TileItem *)(base + fb + ib);
+    Ws ws;
+    ws.hs = (HypState *)(base + o_hs);
+    ws.pose = (PoseEval *)(base + o_pose);
+    ws.hlev = (int *)(base + o_hlev);
+    ws.partials = (float *)(base + o_part);
+    ws.pairs = (unsigned long long *)(base + o_pairs);
+    ws.passflag = (int *)(base + o_flag);
+
+    // descriptors: from a host image the context keeps (pageable; the copy
+    // has consumed it when hipMemcpyAsync returns)
+    std::vector<char> &img = ctx->static_img;
+    img.assign(fb + ib + tb, 0);
+    memcpy(img.data(), plan.frames.data(), plan.frames.size() * sizeof(FrameDev));
+    if (!plan.items.empty()) memcpy(img.data() + fb, plan.items.data(), plan.items.size() * sizeof(WorkItem));
+    if (!plan.tiles.empty()) memcpy(img.data() + fb + ib, plan.tiles.data(), plan.tiles.size() * sizeof(TileItem));
+    HIPCHK(ctx, hipMemcpyAsync(base, img.data(), img.size(), hipMemcpyHostToDevice, ctx->stream));
+    // the pair counters start at zero (a fill kernel, not a memset node)
+    HIPCHK(ctx, launch_zero_words(ws.pairs, (int)(kStatClasses * sizeof(unsigned long long) / 4), ctx->stream));
+    return enqueue_schedule(ctx, plan, dp, ws, ctx->stream, false);
 }
 
 int pilot_linearize(pilot_ctx *ctx, const pilot_frame *frame, int level, const double *poses, double *H21,
@@ -940,10 +1047,10 @@ int pilot_linearize(pilot_ctx *ctx, const pilot_frame *frame, int level, const d
     DevPtrs dp;
     if ((rc = upload_plan(ctx, plan, dp))) return rc;
     if ((rc = enqueue_gram(ctx, plan, dp, ctx->stream))) return rc;
-    HIPCHK(ctx, launch_init(dp.frames, 1, plan.max_M, (HypState *)ctx->hs.p, (PoseEval *)ctx->pose.p,
-                            (int *)ctx->hlev.p, MODE_DIAG, poses, level, ctx->stream));
+    const Ws ws = ws_of(ctx);
+    HIPCHK(ctx, launch_init(dp.frames, 1, plan.max_M, ws.hs, ws.pose, ws.hlev, MODE_DIAG, poses, level, ctx->stream));
     for (const LaunchGroup &g : plan.groups)
-        if ((rc = enqueue_pass(ctx, plan, dp, g, MODE_DIAG, ctx->stream, (ctx->flags & PILOT_FLAG_PROFILE) != 0)))
+        if ((rc = enqueue_pass(ctx, plan, dp, ws, g, MODE_DIAG, ctx->stream, (ctx->flags & PILOT_FLAG_PROFILE) != 0)))
             return rc;
     return PILOT_OK;
 }
@@ -986,7 +1093,7 @@ static int timed_solve(pilot_ctx *ctx, const pilot_frame *frame, const pilot_res
     if ((rc = upload_plan(ctx, plan, dp))) return rc;
     uint64_t launches[kStatClasses];
     memcpy(launches, ctx->launches, sizeof launches);
-    rc = enqueue_schedule(ctx, plan, dp, ctx->stream, true);
+    rc = enqueue_schedule(ctx, plan, dp, ws_of(ctx), ctx->stream, true);
     memcpy(ctx->launches, launches, sizeof launches);
     if (rc) return rc;
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -1432,7 +1539,7 @@ int pilot_step(pilot_ctx *ctx)
     // a launch are at other levels: its epilogues test the tile mask first
     for (int l = 0; l < PILOT_MAX_LEVELS; ++l)
         for (const LaunchGroup &g : plan.groups)
-            if (g.level == l && (rc = enqueue_pass(ctx, plan, dp, g, MODE_LM, ctx->stream,
+            if (g.level == l && (rc = enqueue_pass(ctx, plan, dp, ws_of(ctx), g, MODE_LM, ctx->stream,
                                                    (ctx->flags & PILOT_FLAG_PROFILE) != 0, nullptr, nullptr, true)))
                 return rc;
     bool prunes = false;

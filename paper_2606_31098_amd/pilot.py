@@ -195,6 +195,17 @@ class Context:
         self._check(self.lib.pilot_solve(self.h, fa, n, ra))
         return results
 
+    def solve_static(self, frames: Sequence[DeviceFrame], results: Optional[Sequence[DeviceResult]] = None):
+        """pilot_solve_static: the solve on the library's fixed device scratch
+        (no device allocation; tiles from the tile database or heuristic)."""
+        n = len(frames)
+        if results is None:
+            results = [DeviceResult(f.M, f"cuda:{self.device}") for f in frames]
+        fa = (A.Frame * n)(*[f.s for f in frames])
+        ra = (A.Result * n)(*[r.s for r in results])
+        self._check(self.lib.pilot_solve_static(self.h, fa, n, ra))
+        return results
+
     def solve_raw(self, frame_array, n, result_array):
         """Solve from prebuilt ctypes arrays (used by timing loops)."""
         return self._check(self.lib.pilot_solve(self.h, frame_array, n, result_array))
