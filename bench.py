@@ -3,21 +3,25 @@
 
 One step = one full solve (every level, every LM pass, selection) of the
 workload's frames, inputs resident in HBM before timing starts.  Default
-workload (--config 2): one synthetic frame with 3 levels 120x160x32 /
-240x320x64 / 480x640x128 (f32), N = 8192 anchors per level, M = 256
-hypotheses within 20 m / 10 deg of the prior, 15 LM iterations per level,
-gravity and laser-range priors on.  Other workloads: --config 1 (single
-hypothesis, one 120x160x32 level, latency over many graph replays),
---config 3 (N = 16384, M = 1024, bf16 maps), --config 4 (64 uneven frames
-in one solve), --config 5 (continuous-batching serving of 16 simulated
-30 Hz UAV sequences).
+workload (--config 3, the precision form): one synthetic frame with 3 levels
+120x160x32 / 240x320x64 / 480x640x128 with bf16 maps and descriptors,
+N = 16384 anchors per level, M = 1024 hypotheses within 20 m / 10 deg of the
+prior, 15 LM iterations per level, gravity and laser-range priors on; beside
+it the same frame through the plain FP32 solver (f32 maps) and the FP32
+multi-hypothesis workload (--config 2: N = 8192, M = 256, f32).  Other
+workloads: --config 1 (single hypothesis, one 120x160x32 level, latency over
+many graph replays), --config 4 (64 uneven frames in one solve), --config 5
+(continuous-batching serving of 16 simulated 30 Hz UAV sequences).
 
 Prints one JSON line:
   value        point-residual (anchor x hypothesis) evaluations per second
-  roofline     dominant kernel (finest-level pass kernel): algorithmic
-               gathered bytes (4 taps x C x bytes per element, per
-               evaluation) per launch / average launch duration, from
-               hipEvents on the solver's stream
+  roofline     dominant kernel (finest-level pass kernel): the bytes one
+               launch moves between L2 and HBM/MALL (rocprofv3 FETCH_SIZE +
+               WRITE_SIZE, scaled by a plain copy's reading, stored in
+               profiles/ for the kernel sources it was taken from) / the
+               average launch duration measured here with hipEvents on the
+               solver's stream; beside it the dense-equivalent gathered bytes
+               (4 taps x C x bytes per element for every evaluation)
   cpu_baseline the FP64 oracle on a bounded sample of the same workload
 """
 from __future__ import annotations
@@ -46,10 +50,12 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=None)
     p.add_argument("--warmup", type=int, default=10)
-    p.add_argument("--config", type=int, default=2, choices=[0, 1, 2, 3, 4, 5])
+    p.add_argument("--config", type=int, default=3, choices=[0, 1, 2, 3, 4, 5])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
     p.add_argument("--no-bf16", action="store_true", help="config 2: skip the bf16 comparison")
+    p.add_argument("--no-f32", action="store_true", help="config 3: skip the FP32 solver on the same frame")
+    p.add_argument("--no-config2", action="store_true", help="config 3: skip the config-2 FP32 leg")
     p.add_argument("--frame-seed", type=int, default=0)
     p.add_argument("--no-tune", action="store_true", help="heuristic tiles instead of the autotuner")
     p.add_argument("--tune-cache", default=TILES_FILE,
@@ -130,7 +136,12 @@ def tune(ctx, args, dfs):
 
 def roofline_leg(args, dfs, steps):
     """Profiled solves (per-launch hipEvents around every pass kernel) of
-    the same workload; the finest level's pass kernel is the dominant one."""
+    the same workload; the finest level's pass kernel is the dominant one.
+    The roof is HBM bandwidth: `achieved` is the bytes the launch moves
+    between L2 and HBM/MALL, from the counter profile stored for the current
+    kernel sources (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated), over
+    the launch duration measured here; null when the stored profile is of
+    other sources."""
     from paper_2606_31098_amd import _abi as A
     from paper_2606_31098_amd import build as B
     pctx = make_context(args, A.FLAG_PROFILE)
@@ -139,44 +150,47 @@ def roofline_leg(args, dfs, steps):
     fine = max(l for l in range(A.MAX_LEVELS) if pst.timed_launches[l] > 0)
     n_launch = pst.timed_launches[fine]
     avg_ms = pst.pass_ms[fine] / n_launch
-    bytes_per_launch = pst.pair_bytes[fine] / n_launch
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic, counters = None, None
-    if os.path.exists(TRAFFIC_FILE):
-        try:
-            tj = json.load(open(TRAFFIC_FILE))
-            entry = tj.get(f"config{args.config}")
-            if entry and entry.get("pass_kernel_digest") == B.pass_kernel_digest():
-                traffic = entry.get("bytes_per_launch")
-                # what the counters say bounds the kernel: VALU issue rate and fabric traffic
-                cyc = entry.get("gpu_cycles_per_launch")
-                valu = entry.get("valu_instructions_per_launch")
-                if cyc and valu:
-                    counters = {"valu_issue_frac": round(valu / (VALU_ISSUE_PER_CYCLE * cyc), 3),
-                                "fabric_GBps": round(traffic / (avg_ms * 1e-3) / 1e9, 1),
-                                "fabric_frac_of_hbm": round(traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
-                                "l2_hit_rate": entry.get("l2_hit_rate"),
-                                "texture_addresser_busy": entry.get("texture_addresser_busy"),
-                                "texture_data_busy": entry.get("texture_data_busy"),
-                                "source": "profiles/pass_kernel_traffic.json (rocprofv3 --pmc, same kernel sources)"}
-                    # bytes that actually pass through L1 (the algorithmic bytes count every
-                    # pair's taps; hypotheses sharing a cell share one gather)
-                    l1 = entry.get("l1_bytes_per_launch")
-                    if l1:
-                        counters["l1_bytes_per_launch"] = l1
-                        counters["l1_frac_of_algorithmic"] = round(l1 / bytes_per_launch, 3)
-        except (OSError, ValueError):
-            traffic, counters = None, None
+    dense_bytes = pst.pair_bytes[fine] / n_launch
     C = dfs[0].s.level[fine].C
     dt = "bf16" if dfs[0].s.level[fine].dtype == A.BF16 else "f32"
     pctx.close()
-    log(f"roofline: {achieved:.1f} GB/s ({achieved / HBM_PEAK_GBS:.3f} of HBM peak), {avg_ms:.4f} ms/launch")
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": f"pass_kernel<{C}, {dt}> (level {fine})", "launches": int(n_launch),
-            "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": int(bytes_per_launch),
-            "pairs_per_launch": int(pst.pairs[fine] / n_launch), "counters": counters,
-            "profiled_ms_per_step": round(pwall * 1e3 / steps, 3)}
+    traffic, counters, source = None, None, None
+    digest = B.pass_kernel_digest()
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            entry = json.load(open(TRAFFIC_FILE)).get(f"config{args.config}")
+        except (OSError, ValueError):
+            entry = None
+        if entry and entry.get("pass_kernel_digest") == digest:
+            traffic = entry.get("bytes_per_launch")
+            source = f"{os.path.relpath(TRAFFIC_FILE, ROOT)} [config{args.config}], pass kernel sources {digest}"
+            cyc, valu = entry.get("gpu_cycles_per_launch"), entry.get("valu_instructions_per_launch")
+            counters = {"l2_hit_rate": entry.get("l2_hit_rate"),
+                        "texture_addresser_busy": entry.get("texture_addresser_busy"),
+                        "texture_data_busy": entry.get("texture_data_busy")}
+            if cyc and valu:
+                counters["valu_issue_frac"] = round(valu / (VALU_ISSUE_PER_CYCLE * cyc), 3)
+            if entry.get("l1_bytes_per_launch"):
+                counters["l1_bytes_per_launch"] = entry["l1_bytes_per_launch"]
+    achieved = traffic / (avg_ms * 1e-3) / 1e9 if traffic else None
+    dense_gbs = dense_bytes / (avg_ms * 1e-3) / 1e9
+    if achieved is not None:
+        log(f"roofline: {achieved:.1f} GB/s of HBM/MALL traffic ({achieved / HBM_PEAK_GBS:.3f} of peak), "
+            f"{avg_ms:.4f} ms/launch; dense-equivalent gathers {dense_gbs:.0f} GB/s")
+    else:
+        log(f"roofline: no counter profile of pass kernel sources {digest} for config {args.config}; "
+            f"{avg_ms:.4f} ms/launch")
+    return {"bound": "hbm", "achieved": round(achieved, 1) if achieved is not None else None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved is not None else None,
+            "traffic": traffic, "traffic_source": source,
+            "kernel": f"pass kernel C={C} {dt} (level {fine})", "launches": int(n_launch),
+            "avg_launch_ms": round(avg_ms, 5), "pairs_per_launch": int(pst.pairs[fine] / n_launch),
+            "dense_equivalent": {"bytes_per_launch": int(dense_bytes), "GBps": round(dense_gbs, 1),
+                                 "note": "4 taps x C x element bytes for every evaluated pair; pairs whose "
+                                         "projections share a cell share one gather and the maps stay in "
+                                         "L2/MALL, so this exceeds every memory peak and is not a roofline"},
+            "counters": counters, "profiled_ms_per_step": round(pwall * 1e3 / steps, 3)}
 
 
 def cpu_leg(args, frames):
@@ -268,6 +282,7 @@ def write_tiles(args):
     sets = [(c,) + config_frames(c, 0) for c in (0, 1, 2)]
     sets.append((2, config_frames(2, 0)[0], "bf16"))
     sets += [(c,) + config_frames(c, 0) for c in (3, 4)]
+    sets.append((3, config_frames(3, 0)[0], "f32"))
     serve = [S.make_frame(2, 0, N=side * side // 32, M=m, level_shapes=Q.LEVELS, iters=Q.ITERS, dsm_side=side)
              for side in (128, 256, 512) for m in (64, 128, 256, 512)]
     sets.append(("serving", serve, "bf16"))
@@ -279,69 +294,99 @@ def write_tiles(args):
     ctx.close()
 
 
-def run_solve_config(args):
+def bf16_inputs(frame):
+    """A host copy of the frame with its maps and reference descriptors
+    rounded to bf16 (round-to-nearest-even), the values the device reads."""
+    import copy
+
+    import torch
+    f = copy.deepcopy(frame)
+    for L in f.levels:
+        L.feat = torch.as_tensor(L.feat).to(torch.bfloat16).to(torch.float32).numpy()
+        L.ref = torch.as_tensor(L.ref).to(torch.bfloat16).to(torch.float32).numpy()
+    return f
+
+
+def solve_leg(args, frames, dtype, steps):
+    """Timed solves of one workload (tiles from the database, graph replays).
+    Returns the summary, the per-frame results and the device frames."""
     import numpy as np
     import torch
 
     from paper_2606_31098_amd.pilot import DeviceFrame
     from synth import frames as S
-
-    cfg = args.config
-    t = time.perf_counter()
-    frames, dtype = config_frames(cfg, args.frame_seed)
-    log(f"generated {len(frames)} frame(s) in {time.perf_counter() - t:.1f}s")
     dfs = [DeviceFrame(f, dtype=dtype) for f in frames]
     torch.cuda.synchronize()
-    steps = args.steps or {0: 50, 1: 1000, 2: 50, 3: 50, 4: 20}[cfg]
-
     ctx = make_context(args)
     tune_s = tune(ctx, args, dfs)
     tiles = sorted({ctx.tile_choice(L.C, L.dtype, L.N, d.M, L.H * L.W) for d in dfs for L in d.s.level[:d.s.n_levels]})
     log(f"tiles ({tune_s:.1f}s): {tiles[:6]}")
     wall, lat, st, res = timed_solves(ctx, dfs, steps, args.warmup)
     pairs = sum(st.pairs)
-    ms = wall * 1e3 / steps
-    evals = pairs / wall
-    gbs = sum(st.pair_bytes) / wall / 1e9
     outs = [r.numpy() for r in res]
     errs = [S.pose_errors(o["poses"][o["best"]], f.gt_pose) for o, f in zip(outs, frames)]
     te = [e[0][0] for e in errs]
     re_ = [e[1][0] for e in errs]
-    log(f"solve: {ms:.3f} ms/step, {evals:.4g} evals/s, {gbs:.1f} GB/s algorithmic, "
+    out = {"value": pairs / wall, "ms_per_step": wall * 1e3 / steps, "evals_per_step": pairs / steps,
+           "gb_per_s_dense_equivalent": sum(st.pair_bytes) / wall / 1e9,
+           "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)}, "tiles": tiles,
+           "best_pose_error": {"median_m": float(np.median(te)), "median_deg": float(np.median(re_))},
+           "graph": {"captures": st.graph_captures, "replays": st.graph_replays}}
+    log(f"solve {dtype}: {out['ms_per_step']:.3f} ms/step, {out['value']:.4g} evals/s, "
         f"best-pose error median {np.median(te):.3f} m / {np.median(re_):.4f} deg")
-    extra = {"gb_per_s_algorithmic": gbs, "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
-             "evals_per_step": pairs / steps, "tiles": tiles,
-             "best_pose_error": {"median_m": float(np.median(te)), "median_deg": float(np.median(re_))},
-             "graph": {"captures": st.graph_captures, "replays": st.graph_replays}}
+    return out, outs, dfs, ctx
+
+
+def run_solve_config(args):
+    cfg = args.config
+    t = time.perf_counter()
+    frames, dtype = config_frames(cfg, args.frame_seed)
+    log(f"generated {len(frames)} frame(s) in {time.perf_counter() - t:.1f}s")
+    steps = args.steps or {0: 50, 1: 1000, 2: 50, 3: 30, 4: 20}[cfg]
+
+    head, outs, dfs, ctx = solve_leg(args, frames, dtype, steps)
+    extra = {k: head[k] for k in ("gb_per_s_dense_equivalent", "latency_ms", "evals_per_step", "tiles",
+                                  "best_pose_error", "graph")}
     extra["roofline"] = roofline_leg(args, dfs, max(2, min(steps, 5)))
     if cfg == 4:
+        import numpy as np
         # batch invariance: frame 0 alone equals frame 0 inside the batch
         alone = ctx.solve([dfs[0]])[0].numpy()
         extra["batch_invariance_frame0_bitwise"] = bool(
             np.array_equal(alone["poses"], outs[0]["poses"]) and np.array_equal(alone["cost"], outs[0]["cost"]))
+    ctx.close()
+    del dfs
+    other = {}
     if cfg == 2 and not args.no_bf16:
-        dfb = DeviceFrame(frames[0], dtype="bf16")
-        bctx = make_context(args)
-        tune(bctx, args, [dfb])
-        bwall, blat, bst, bres = timed_solves(bctx, [dfb], steps, args.warmup)
-        bo = bres[0].numpy()
-        bf16_result = bo
-        bte, bre = S.pose_errors(bo["poses"][bo["best"]], frames[0].gt_pose)
-        bms = bwall * 1e3 / steps
-        extra["bf16_same_workload"] = {
-            "value": sum(bst.pairs) / bwall, "ms_per_step": bms, "evals_per_step": sum(bst.pairs) / steps,
-            "latency_ms": {"p50": percentile(blat, 50), "p99": percentile(blat, 99)},
-            "solve_speedup_vs_f32": ms / bms, "best_pose_error_m": float(bte[0]),
-            "best_pose_error_deg": float(bre[0])}
-        log(f"bf16: {bms:.3f} ms/step ({ms / bms:.2f}x per solve)")
+        b, bo, bdfs, bctx = solve_leg(args, frames, "bf16", steps)
         bctx.close()
-    extra["cpu_baseline"], orc = cpu_leg(args, frames)
+        b["solve_speedup_vs_f32"] = head["ms_per_step"] / b["ms_per_step"]
+        extra["bf16_same_workload"] = b
+        other["bf16"] = bo[0]
+    if cfg == 3 and not args.no_f32:
+        # the plain FP32 solver on the same frame (f32 maps and descriptors)
+        f32, fo, fdfs, fctx = solve_leg(args, frames, "f32", steps)
+        fctx.close()
+        del fdfs
+        f32["bf16_speedup_vs_f32"] = f32["ms_per_step"] / head["ms_per_step"]
+        extra["f32_same_workload"] = f32
+        log(f"bf16 vs f32 on the same frame: {f32['bf16_speedup_vs_f32']:.2f}x per solve")
+    if cfg == 3 and not args.no_config2:
+        c2frames, _ = config_frames(2, args.frame_seed)
+        c2, _, c2dfs, c2ctx = solve_leg(args, c2frames, "f32", 50)
+        c2ctx.close()
+        del c2dfs
+        extra["config2_f32"] = c2
+    # the oracle on the inputs the headline solve read (bf16-rounded when bf16)
+    ofr = [bf16_inputs(frames[0])] if dtype == "bf16" else frames[:1]
+    extra["cpu_baseline"], orc = cpu_leg(args, ofr)
     if orc is not None and getattr(frames[0], "keep_top", 0) and len(orc["index"]) < frames[0].M:
         orc = None                   # a pruned subset ranks differently from the full set
     if orc is not None:
-        extra["vs_oracle"] = {"f32" if dtype == "f32" else dtype: vs_oracle(frames[0], outs[0], orc)}
-        if cfg == 2 and not args.no_bf16:
-            extra["vs_oracle"]["bf16 (oracle on the f32 inputs)"] = vs_oracle(frames[0], bf16_result, orc)
+        key = f"{dtype} (oracle on the same {dtype}-valued inputs)"
+        extra["vs_oracle"] = {key: vs_oracle(ofr[0], outs[0], orc)}
+        if "bf16" in other:
+            extra["vs_oracle"]["bf16 (oracle on the f32 inputs)"] = vs_oracle(frames[0], other["bf16"], orc)
         log(f"vs oracle: {extra['vs_oracle']}")
     names = {0: "paper-shaped context: 1 frame, N=500 anchors, 1210-hypothesis grid (+-10 m, 2 m, yaw +-1..9 deg) "
                 "pruned to the top 128 after the coarse level, 3 levels 120x160 / 240x320 / 480x640 with C=32 f32, "
@@ -349,14 +394,14 @@ def run_solve_config(args):
              1: "1 frame, 1 hypothesis, N=1024 anchors from a 64x64 DSM, one 120x160x32 f32 level, 20 LM iterations",
              2: "1 frame, 3 levels 120x160x32 / 240x320x64 / 480x640x128 f32, N=8192 anchors, M=256 hypotheses "
                 "(20 m / 10 deg), 15 LM iterations per level, gravity + range priors",
-             3: "1 frame, 3 levels 120x160x32 / 240x320x64 / 480x640x128 bf16 maps (FP64 projection/cost, "
-                "FP32 Jacobian sums, FP64 solve/pose), N=16384 anchors, M=1024 hypotheses, 15 iterations per level",
+             3: "precision form: 1 frame, 3 levels 120x160x32 / 240x320x64 / 480x640x128 with bf16 maps and "
+                "descriptors, N=16384 anchors, M=1024 hypotheses (20 m / 10 deg), 15 LM iterations per level, "
+                "gravity + range priors",
              4: "64 frames in one solve: N log-uniform 2048..32768, M in {32..512}, finest level 240x320 / 360x480 / "
                 "480x640, C 32/64/128 bf16, 15 iterations per level"}
     workload = {"workload": names[cfg], "frames": len(frames),
-                "hypotheses": int(sum(d.M for d in dfs)), "anchors": int(sum(d.s.level[0].N for d in dfs))}
-    ctx.close()
-    return line(args, evals, steps, args.warmup, ms, dtype, workload, extra)
+                "hypotheses": int(sum(f.M for f in frames)), "anchors": int(sum(f.levels[0].N for f in frames))}
+    return line(args, head["value"], steps, args.warmup, head["ms_per_step"], dtype, workload, extra)
 
 
 class _RawFrame:
@@ -516,7 +561,7 @@ def run_serving_config(args, worlds):
                          "within_1m_1deg": float(np.mean((te <= 1) & (re_ <= 1))),
                          "host_seconds": {"prepare": st.host_prepare, "admit": st.host_admit,
                                           "step": st.host_step, "poll": st.host_poll}},
-             "gb_per_s_algorithmic": sum(counters.pair_bytes) / st.wall / 1e9,
+             "gb_per_s_dense_equivalent": sum(counters.pair_bytes) / st.wall / 1e9,
              "roofline": None, "cpu_baseline": None}
     ctx.close()
     return line(args, pairs / st.wall, st.steps, 0, st.wall * 1e3 / max(st.steps, 1), "bf16", workload, extra)
