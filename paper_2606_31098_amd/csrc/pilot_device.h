@@ -27,8 +27,9 @@ struct LevelDev {
     int iters, loss_kind;
     double loss_b;
     int dtype, pad;
-    // pass kernel variants 3 to 8: per-cell Gram matrices of the bilinear
-    // coefficients, 10 doubles per cell (x0, y0) at index y0 W + x0
+    // pass kernel variants 3 to 10: per-cell Gram matrices of the bilinear
+    // coefficients of cell (x0, y0) at index y0 W + x0, 10 doubles per cell
+    // (variants 3 to 8) or 12 floats (variants 9 and 10: 10 entries, 2 pads)
     const double *gram;
 };
 

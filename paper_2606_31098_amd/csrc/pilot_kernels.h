@@ -10,7 +10,8 @@ struct TileConfig {
     int PPG = 1;        // anchors per lane group per work item
     int grid = 0;       // blocks per CU of a persistent grid (0: one block per item); launch: blocks
     int variant = 1;    // pass kernel: 1 batch-then-compute loop, 2 software-pipelined loop,
-                        // 3-8 per-cell Gram tables (see pilot_pass3.inc)
+                        // 3-8 per-cell Gram tables (see pilot_pass3.inc), 9-10 the same with
+                        // FP32 arithmetic on the per-pair path for bf16 maps (pilot_pass4.inc)
 };
 
 // True if a pass kernel exists for (C, dtype, G).
@@ -35,12 +36,13 @@ hipError_t launch_init(const FrameDev *frames, int n_frames, int max_M, HypState
                        int flag_stride = 1);
 
 // Per-cell Gram matrices of the bilinear coefficients of the feature map of
-// level `level` of frames[frame] (pass kernel variants 3 to 8): 10 doubles
-// per cell, cells y0 W + x0, written to that level's `gram`.  The kernel
-// reads the map, its shape and the table pointer from the device descriptor;
-// H, W, C and dtype (the host's copy of them) size the grid and pick the
-// instantiation.
-hipError_t launch_gram(const FrameDev *frames, int frame, int level, int H, int W, int C, int dtype,
+// level `level` of frames[frame] (pass kernel variants 3 to 10), cells
+// y0 W + x0, written to that level's `gram`: fmt 0, 10 doubles per cell
+// (variants 3 to 8); fmt 1, 12 floats per cell, the 10 entries and two zero
+// pads (variants 9 and 10).  The kernel reads the map, its shape and the
+// table pointer from the device descriptor; H, W, C and dtype (the host's
+// copy of them) size the grid and pick the instantiation.
+hipError_t launch_gram(const FrameDev *frames, int frame, int level, int H, int W, int C, int dtype, int fmt,
                        hipStream_t s);
 
 // Geo-anchor lift and reference-descriptor sampling (see pilot_lift).

@@ -495,7 +495,9 @@ __device__ __forceinline__ double quad_sum(double v)
 // The map, its shape and the table are read from the frame descriptor in
 // device memory (not passed by value), so a captured graph replayed for a new
 // frame of the same shape builds the new frame's tables.
-template <int DT>
+// F32: the record format of pass variants 9 and 10, the ten entries rounded
+// to FP32 and two zero pads (48 bytes per cell); otherwise ten FP64 entries.
+template <int DT, bool F32>
 __global__ __launch_bounds__(256) void gram_kernel(const FrameDev *frames, int fi, int level)
 {
     const LevelDev &L = frames[fi].lv[level];
@@ -540,20 +542,33 @@ __global__ __launch_bounds__(256) void gram_kernel(const FrameDev *frames, int f
 #pragma unroll
     for (int i = 0; i < 10; ++i) k[i] = quad_sum(k[i]);
     if (work) {
-        double *out = gram + (size_t)10 * cell;
-        for (int i = q; i < 10; i += 4) out[i] = k[i];
+        if constexpr (F32) {
+            float *out = (float *)gram + (size_t)12 * cell;
+            for (int i = q; i < 12; i += 4) out[i] = i < 10 ? (float)k[i] : 0.0f;
+        } else {
+            double *out = gram + (size_t)10 * cell;
+            for (int i = q; i < 10; i += 4) out[i] = k[i];
+        }
     }
 }
 
-hipError_t launch_gram(const FrameDev *frames, int frame, int level, int H, int W, int C, int dtype, hipStream_t s)
+hipError_t launch_gram(const FrameDev *frames, int frame, int level, int H, int W, int C, int dtype, int fmt,
+                       hipStream_t s)
 {
     const long cells = (long)H * W;
     if (cells <= 0 || C % 16) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((4 * cells + 255) / 256)), block(256);
-    if (dtype == 0)
-        hipLaunchKernelGGL(gram_kernel<0>, grid, block, 0, s, frames, frame, level);
-    else
-        hipLaunchKernelGGL(gram_kernel<1>, grid, block, 0, s, frames, frame, level);
+    if (fmt == 1) {
+        if (dtype == 0)
+            hipLaunchKernelGGL((gram_kernel<0, true>), grid, block, 0, s, frames, frame, level);
+        else
+            hipLaunchKernelGGL((gram_kernel<1, true>), grid, block, 0, s, frames, frame, level);
+    } else {
+        if (dtype == 0)
+            hipLaunchKernelGGL((gram_kernel<0, false>), grid, block, 0, s, frames, frame, level);
+        else
+            hipLaunchKernelGGL((gram_kernel<1, false>), grid, block, 0, s, frames, frame, level);
+    }
     return hipGetLastError();
 }
 

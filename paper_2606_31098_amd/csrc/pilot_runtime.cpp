@@ -66,6 +66,7 @@ struct Plan {
     struct GramJob {
         int frame, level;
         size_t offset;
+        int fmt;
     };
     std::vector<GramJob> gram_jobs;
     size_t gram_bytes = 0;
@@ -340,8 +341,11 @@ void *stage_acquire(pilot_ctx *ctx, size_t bytes, int *which, int *rc)
 }
 
 // ---------------------------------------------------------------- tiles
-// pass variants 3 to 8 read per-cell Gram tables
-bool uses_gram(const TileConfig &tc) { return tc.variant >= 3 && tc.variant <= 8; }
+// pass variants 3 to 10 read per-cell Gram tables: 10 doubles per cell
+// (format 0) or, for variants 9 and 10 on bf16 maps, 12 floats (format 1;
+// on f32 maps those variants run variants 3 and 4)
+bool uses_gram(const TileConfig &tc) { return tc.variant >= 3 && tc.variant <= 10; }
+int gram_format(const TileConfig &tc, int dtype) { return (tc.variant >= 9 && dtype == PILOT_BF16) ? 1 : 0; }
 
 int log2_bucket(int n)
 {
@@ -390,9 +394,10 @@ TileConfig serving_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M, lo
     return choose_tile(ctx, C, dtype, N, M, HW);
 }
 
-size_t gram_table_bytes(const pilot_level &L)
+size_t gram_table_bytes(const pilot_level &L, int fmt)
 {
-    return ((size_t)L.H * L.W * 10 * sizeof(double) + 255) & ~(size_t)255;
+    const size_t per_cell = fmt == 1 ? 12 * sizeof(float) : 10 * sizeof(double);
+    return ((size_t)L.H * L.W * per_cell + 255) & ~(size_t)255;
 }
 
 int n_ptiles_of(const TileConfig &tc, int N)
@@ -549,10 +554,12 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
             if (uses_gram(g.tc))
                 for (int i : kv.second) {
                     const pilot_level &Li = frames[i].level[l];
-                    plan.gram_jobs.push_back(Plan::GramJob{i, l, plan.gram_bytes});
-                    plan.gram_bytes += ((size_t)Li.H * Li.W * 10 * sizeof(double) + 255) & ~(size_t)255;
+                    const int fmt = gram_format(g.tc, Li.dtype);
+                    plan.gram_jobs.push_back(Plan::GramJob{i, l, plan.gram_bytes, fmt});
+                    plan.gram_bytes += gram_table_bytes(Li, fmt);
                     // a captured graph bakes in each Gram launch's grid and instantiation
-                    key << "|g" << i << "." << l << ":" << Li.H << "x" << Li.W << "x" << Li.C << "d" << Li.dtype;
+                    key << "|g" << i << "." << l << ":" << Li.H << "x" << Li.W << "x" << Li.C << "d" << Li.dtype
+                        << "f" << fmt;
                 }
             plan.partial_floats = std::max(plan.partial_floats, (size_t)g.n_items * g.tc.G * kNV);
             plan.groups.push_back(g);
@@ -718,7 +725,7 @@ int enqueue_gram(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, hipStream_
 {
     for (const Plan::GramJob &j : plan.gram_jobs) {
         const LevelDev &L = plan.frames[j.frame].lv[j.level];
-        HIPCHK(ctx, launch_gram(dp.frames, j.frame, j.level, L.H, L.W, L.C, L.dtype, s));
+        HIPCHK(ctx, launch_gram(dp.frames, j.frame, j.level, L.H, L.W, L.C, L.dtype, j.fmt, s));
     }
     return PILOT_OK;
 }
@@ -757,7 +764,7 @@ void load_tune_cache(pilot_ctx *ctx)
     std::string key;
     TileConfig tc{};
     while (in >> key >> tc.G >> tc.PPG >> tc.grid >> tc.variant)
-        if (pass_supported(16, 0, tc.G) && tc.PPG >= 1 && tc.PPG <= 64 && tc.variant >= 1 && tc.variant <= 8)
+        if (pass_supported(16, 0, tc.G) && tc.PPG >= 1 && tc.PPG <= 64 && tc.variant >= 1 && tc.variant <= 10)
             ctx->tuned[key] = tc;
 }
 
@@ -1132,11 +1139,11 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
     if ((rc = collect_timings(ctx))) return rc;           // earlier profiled launches go to the counters
 
     std::vector<TileConfig> cand;
-    // variants 5, 6 and 8 differ from 3, 4 and 7 for bf16 maps only
+    // variants 5, 6, 8, 9 and 10 differ from 3, 4, 7, 3 and 4 for bf16 maps only
     bool bf16 = false;
     for (int l = 0; l < frame->n_levels; ++l) bf16 = bf16 || frame->level[l].dtype == PILOT_BF16;
-    for (int variant : {1, 2, 3, 4, 5, 6, 7, 8}) {
-        if ((variant == 5 || variant == 6 || variant == 8) && !bf16) continue;
+    for (int variant : {1, 2, 3, 4, 5, 6, 7, 8, 9, 10}) {
+        if ((variant == 5 || variant == 6 || variant >= 8) && !bf16) continue;
         for (int G : {4, 8, 16})
             for (int ppg : {2, 4, 8, 16})
                 for (int bpc : {0, 2, 4}) cand.push_back(TileConfig{G, ppg, bpc, variant});
@@ -1292,7 +1299,7 @@ size_t frame_cost(const pilot_ctx *ctx, const pilot_frame &f)
         if (L.qconf) in += (size_t)L.H * L.W * sizeof(float);
         if (L.ref_w) in += (size_t)L.N * sizeof(float);
         const TileConfig tc = choose_tile(ctx, L.C, L.dtype, L.N, f.M, (long)L.H * L.W);
-        if (uses_gram(tc)) in += gram_table_bytes(L);
+        if (uses_gram(tc)) in += gram_table_bytes(L, gram_format(tc, L.dtype));
         const size_t items = (size_t)((f.M + tc.G - 1) / tc.G) * n_ptiles_of(tc, L.N);
         part = std::max(part, items * tc.G * kNV * sizeof(float));
     }
@@ -1469,12 +1476,15 @@ int pilot_admit(pilot_ctx *ctx, const pilot_frame *frame, const pilot_result *re
     ServingSlot &sl = ctx->slots[s];
     size_t gbytes = 0, goff[PILOT_MAX_LEVELS] = {0};
     bool gneed[PILOT_MAX_LEVELS] = {false};
+    int gfmt[PILOT_MAX_LEVELS] = {0};
     for (int l = 0; l < frame->n_levels; ++l) {
         const pilot_level &L = frame->level[l];
-        if (uses_gram(serving_tile(ctx, L.C, L.dtype, L.N, frame->M, (long)L.H * L.W))) {
+        const TileConfig tc = serving_tile(ctx, L.C, L.dtype, L.N, frame->M, (long)L.H * L.W);
+        if (uses_gram(tc)) {
             gneed[l] = true;
+            gfmt[l] = gram_format(tc, L.dtype);
             goff[l] = gbytes;
-            gbytes += gram_table_bytes(L);
+            gbytes += gram_table_bytes(L, gfmt[l]);
         }
     }
     if (gbytes) {
@@ -1501,7 +1511,7 @@ int pilot_admit(pilot_ctx *ctx, const pilot_frame *frame, const pilot_result *re
     for (int l = 0; l < frame->n_levels; ++l)
         if (gneed[l]) {
             const pilot_level &L = frame->level[l];
-            HIPCHK(ctx, launch_gram(dst, 0, l, L.H, L.W, L.C, L.dtype, ctx->stream));
+            HIPCHK(ctx, launch_gram(dst, 0, l, L.H, L.W, L.C, L.dtype, gfmt[l], ctx->stream));
         }
     sl.dev = d;
     sl.active = true;

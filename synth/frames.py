@@ -225,7 +225,7 @@ RANGE_GATE = 5.0 * RANGE_NOISE_M
 
 LM_DEFAULTS = dict(tau=1e-6, up=10.0, down=10.0, lambda_min_rel=1e-12,
                    lambda_max_rel=1e8, step_tol_t=1e-5, step_tol_r=1e-7,
-                   z_min=0.1, min_valid=8, cost_tol=1e-10)
+                   z_min=0.1, min_valid=8, cost_tol=1e-6)
 
 
 @dataclass
