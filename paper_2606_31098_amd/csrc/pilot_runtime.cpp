@@ -380,10 +380,19 @@ TileConfig heuristic_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M, 
     return tc;
 }
 
+// Lane groups of 4, 8 or 16 lanes exist for every variant; variants 9 and 10
+// on bf16 maps also take 1 lane (C <= 32) and 2 lanes (C <= 64).
+bool tile_ok(const TileConfig &tc, int C, int dtype)
+{
+    if (tc.G == 4 || tc.G == 8 || tc.G == 16) return true;
+    if (dtype != PILOT_BF16 || tc.variant < 9) return false;
+    return (tc.G == 1 && C <= 32) || (tc.G == 2 && C <= 64);
+}
+
 TileConfig choose_tile(const pilot_ctx *ctx, int C, int dtype, int N, int M, long HW)
 {
     auto it = ctx->tuned.find(tune_key(C, dtype, N, M, HW));
-    if (it != ctx->tuned.end()) return it->second;
+    if (it != ctx->tuned.end() && tile_ok(it->second, C, dtype)) return it->second;
     return heuristic_tile(ctx, C, dtype, N, M, HW);
 }
 
@@ -764,7 +773,8 @@ void load_tune_cache(pilot_ctx *ctx)
     std::string key;
     TileConfig tc{};
     while (in >> key >> tc.G >> tc.PPG >> tc.grid >> tc.variant)
-        if (pass_supported(16, 0, tc.G) && tc.PPG >= 1 && tc.PPG <= 64 && tc.variant >= 1 && tc.variant <= 10)
+        if ((tc.G == 1 || tc.G == 2 || tc.G == 4 || tc.G == 8 || tc.G == 16) && tc.PPG >= 1 && tc.PPG <= 64 &&
+            tc.variant >= 1 && tc.variant <= 10)
             ctx->tuned[key] = tc;
 }
 
@@ -1129,11 +1139,15 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
     HIPCHK(ctx, hipSetDevice(ctx->device));
     std::vector<std::string> keys(frame->n_levels);
     std::vector<std::string> todo;
+    std::vector<int> todo_C, todo_dt;
     for (int l = 0; l < frame->n_levels; ++l) {
         const pilot_level &L = frame->level[l];
         keys[l] = tune_key(L.C, L.dtype, L.N, frame->M, (long)L.H * L.W);
-        if (!ctx->tuned.count(keys[l]) && std::find(todo.begin(), todo.end(), keys[l]) == todo.end())
+        if (!ctx->tuned.count(keys[l]) && std::find(todo.begin(), todo.end(), keys[l]) == todo.end()) {
             todo.push_back(keys[l]);
+            todo_C.push_back(L.C);
+            todo_dt.push_back(L.dtype);
+        }
     }
     if (todo.empty()) return PILOT_OK;
     if ((rc = collect_timings(ctx))) return rc;           // earlier profiled launches go to the counters
@@ -1144,9 +1158,11 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
     for (int l = 0; l < frame->n_levels; ++l) bf16 = bf16 || frame->level[l].dtype == PILOT_BF16;
     for (int variant : {1, 2, 3, 4, 5, 6, 7, 8, 9, 10}) {
         if ((variant == 5 || variant == 6 || variant >= 8) && !bf16) continue;
-        for (int G : {4, 8, 16})
+        for (int G : {1, 2, 4, 8, 16}) {
+            if (G < 4 && variant < 9) continue;          // narrow lane groups: variants 9 and 10 only
             for (int ppg : {2, 4, 8, 16})
                 for (int bpc : {0, 2, 4}) cand.push_back(TileConfig{G, ppg, bpc, variant});
+        }
     }
 
     // scratch outputs of the timed solves
@@ -1177,7 +1193,8 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
             const auto it = std::find(todo.begin(), todo.end(), keys[l]);
             if (it != todo.end()) per[it - todo.begin()] += ms[l];
         }
-        for (size_t k = 0; k < todo.size(); ++k) score[c][k] = std::min(score[c][k], per[k]);
+        for (size_t k = 0; k < todo.size(); ++k)
+            if (tile_ok(cand[c], todo_C[k], todo_dt[k])) score[c][k] = std::min(score[c][k], per[k]);
         return PILOT_OK;
     };
 
@@ -1239,8 +1256,9 @@ int pilot_tile_choice(pilot_ctx *ctx, int C, int dtype, int N, int M, int64_t HW
 {
     if (!ctx || !buf || buflen < 1) return fail(ctx, PILOT_EINVAL, "ctx/buf: invalid");
     TileConfig tc = choose_tile(ctx, C, dtype, N, M, (long)HW);
+    auto it = ctx->tuned.find(tune_key(C, dtype, N, M, (long)HW));
     snprintf(buf, buflen, "G=%d PPG=%d BPC=%d V=%d tuned=%d", tc.G, tc.PPG, tc.grid, tc.variant,
-             (int)ctx->tuned.count(tune_key(C, dtype, N, M, (long)HW)));
+             (int)(it != ctx->tuned.end() && tile_ok(it->second, C, dtype)));
     return PILOT_OK;
 }
 

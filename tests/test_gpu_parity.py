@@ -1,5 +1,6 @@
 """GPU path (libpilot, through the C ABI) against the FP64 oracle, element by
 element on the same seeded inputs."""
+import copy
 import math
 
 import numpy as np
@@ -218,6 +219,49 @@ def test_tile_shapes_and_kernel_variants_match_oracle(tmp_path, variant, G, dtyp
     orc = oracle.solve(f, threads=8)
     rows, fails = compare_solutions(f, gpu, orc, tol_m, tol_deg, f"v{variant}G{G}{dtype}")
     assert not fails, fails
+
+
+@pytest.mark.parametrize("variant", [9, 10])
+@pytest.mark.parametrize("G", [1, 2])
+def test_narrow_lane_groups_match_oracle(tmp_path, variant, G):
+    """Variants 9 and 10 on bf16 maps with lane groups of 1 lane (C <= 32) and
+    2 lanes (C <= 64): normal equations, cost and solves against the oracle
+    on the same rounded inputs, at the bf16 bar.  Levels whose C is too wide
+    for the group fall back to the built-in tile (checked)."""
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    f = bf16_copy(pyramid_frame(seed=18, N=900, M=11, iters=(4, 4, 4)))
+    cache = tmp_path / "tune.txt"
+    with open(cache, "w") as fh:
+        for L in f.levels:
+            fh.write(f"C{L.C}_d1_N{_floor_log2(L.N)}_M{_floor_log2(f.M)}_P{_floor_log2(L.H * L.W)}_v3 "
+                     f"{G} 4 0 {variant}\n")
+    c = Context(0, tune_cache=str(cache))
+    for L in f.levels:
+        want = L.C <= (32 if G == 1 else 64)
+        got = c.tile_choice(L.C, 1, L.N, f.M, L.H * L.W)
+        assert (f"G={G} " in got and f"V={variant}" in got) == want, (L.C, got)
+    rng = np.random.default_rng(3)
+    poses = np.stack([oracle.compose(oracle.se3_exp(np.concatenate([rng.normal(0, 2, 3), rng.normal(0, 0.02, 3)])),
+                                     f.gt_pose) for _ in range(f.M)])
+    fm = mask_edges(copy.deepcopy(f), poses)
+    df = DeviceFrame(fm, dtype="bf16")
+    of = oracle.OracleFrame(fm)
+    say(f"narrow lane groups: variant={variant} G={G}")
+    for lvl in range(3):
+        H21, g, cost, n = c.linearize(df, lvl, torch.as_tensor(poses, device="cuda"))
+        torch.cuda.synchronize()
+        H = unpack_h21(H21.cpu().numpy())
+        g, cost = g.cpu().numpy(), cost.cpu().numpy()
+        for m in range(f.M):
+            Ho, go, co, no = oracle.linearize(of, lvl, poses[m])
+            err = rel_frobenius(np.concatenate([H[m], g[m][:, None]], 1), np.concatenate([Ho, go[:, None]], 1))
+            assert err <= 1e-4, (lvl, m, err)
+            assert abs(cost[m] - co) <= 1e-5 * abs(co), (lvl, m, (cost[m] - co) / co)
+    gpu = c.solve([DeviceFrame(f, dtype="bf16")])[0].numpy()
+    orc = oracle.solve(f, threads=8)
+    rows, fails = compare_solutions(f, gpu, orc, BF16_TOL_M, BF16_TOL_DEG, f"v{variant}G{G}")
+    assert not fails, fails
+    c.close()
 
 
 @pytest.mark.parametrize("scale", [1e-9, 1e-6, 1e-3, 1.0, 1e3, 1e6, 1e9])
