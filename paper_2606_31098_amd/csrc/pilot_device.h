@@ -94,7 +94,9 @@ struct HypState {
     double g[6];
     double cost, lam, lmin, lmax;
     double alpha[2]; // prior scales (gravity, range) of the current level
-    int level, phase, it_level, it_total, status, nvalid, pad0, pad1;
+    int level, phase, it_level, it_total, status, nvalid;
+    int home;        // the hypothesis' own (global) index: packed copies of the state carry it
+    int pad1;
 };
 
 enum { PHASE_START = 0, PHASE_CAND = 1 };
@@ -118,6 +120,18 @@ struct PassArgs {
     const int *hlev;             // level whose evaluation is pending; -1 finished
     float *partials;             // [item][G][kNV]
     const int *run_flag;         // NULL, or 0 when no hypothesis is at this level (the launch has nothing to do)
+    // Packed hypothesis tiles (pass variants 3 to 10), or NULL: the tile whose
+    // first hypothesis index is hb holds, instead of hypotheses hb .. hb + G - 1,
+    // the packed entries hb .. hb + G - 1 of the hypotheses still at the level
+    // (pcount[frame] of them from the frame's hyp_base on; their poses under
+    // evaluation are ppose[hb + hh]); tiles past that count have nothing to do.
+    // Block 0 clears pcount_clear[0 .. n_frames) (the counts the pass's
+    // epilogue appends to).
+    const PoseEval *ppose;
+    const int *pcount;
+    int *pcount_clear;
+    int n_frames;
+    int pack_min;                // see use_packed
 };
 
 struct EpilogueArgs {
@@ -135,6 +149,32 @@ struct EpilogueArgs {
     int *next_flag;              // NULL, or set to 1 when a hypothesis stays at this level
     int mask_first;              // test the tile mask before fetching the partial sums (launches
                                  // where most tiles are at other levels), else after
+    // packed hypothesis tiles (as in PassArgs), or NULL: slot hh of the tile
+    // is packed entry hb + hh, whose LM state and pose are phs / ppose[hb + hh]
+    // (the state's `home` is the hypothesis' own index, where its state and
+    // pose are also written back); the hypotheses that stay at the level are
+    // appended (tiles in order of arrival, a tile's in slot order) to
+    // phs_next / ppose_next, counted in pcount_next, for the next pass
+    const HypState *phs;
+    const PoseEval *ppose;
+    const int *pcount;
+    HypState *phs_next;
+    PoseEval *ppose_next;
+    int *pcount_next;
+    int pack_min;                // see use_packed
 };
+
+// Packed or contiguous hypothesis tiles for one frame in one pass: packed when
+// the tiles a contiguous walk may find active (at most one per hypothesis
+// still at the level, at most every tile) hold more than pack_min work items,
+// i.e. when packing saves rounds of blocks; below that the contiguous tiles
+// fit in one round and packing would only put more distinct cells into fewer
+// items.  The pass kernel and its epilogue take the decision from the same
+// count, and sums do not depend on the tiling: results are the same either way.
+__host__ __device__ inline bool use_packed(int count, int M, int G, int npt, int pack_min)
+{
+    const int tiles = (M + G - 1) / G;
+    return (long long)(count < tiles ? count : tiles) * npt > pack_min;
+}
 
 }  // namespace pilot

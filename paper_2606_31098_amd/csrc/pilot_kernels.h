@@ -6,12 +6,14 @@
 namespace pilot {
 
 struct TileConfig {
-    int G = 4;          // lanes per anchor = hypotheses per tile (4, 8 or 16)
+    int G = 4;          // lanes per anchor = hypotheses per tile (1 to 16)
     int PPG = 1;        // anchors per lane group per work item
     int grid = 0;       // blocks per CU of a persistent grid (0: one block per item); launch: blocks
     int variant = 1;    // pass kernel: 1 batch-then-compute loop, 2 software-pipelined loop,
                         // 3-8 per-cell Gram tables (see pilot_pass3.inc), 9-10 the same with
                         // FP32 arithmetic on the per-pair path for bf16 maps (pilot_pass4.inc)
+    int pack = 0;       // variants 3-10: hypothesis tiles 0 contiguous, 1 packed when that saves
+                        // rounds of blocks (use_packed), 2 packed whenever hypotheses remain
 };
 
 // True if a pass kernel exists for (C, dtype, G).
@@ -53,6 +55,15 @@ hipError_t launch_lift(const float *dsm, int Hd, int Wd, double x0, double y0, d
 // Top-K pruning of frames whose hypotheses all finished their pruning level.
 hipError_t launch_prune(const FrameDev *frames, int n_frames, HypState *hs, PoseEval *pose, int *hlev,
                         hipStream_t s);
+
+// Per frame: the LM states and poses under evaluation of the hypotheses whose
+// pending level is `level`, in index order, to phs / ppose[hyp_base ..), their
+// number to pcount[frame], and the frame's counts in pclear0 / pclear1 set to
+// zero (the packed hypothesis tiles of a level's first pass; see
+// PassArgs::ppose and EpilogueArgs::phs).
+hipError_t launch_pack(const FrameDev *frames, int n_frames, int max_M, const int *hlev, int level,
+                       const HypState *hs, const PoseEval *pose, HypState *phs, PoseEval *ppose, int *pcount,
+                       int *pclear0, int *pclear1, hipStream_t s);
 
 // Write results of every frame whose hypotheses have all finished and that
 // has not been finalised yet (done_flag == 0), including the argmin.

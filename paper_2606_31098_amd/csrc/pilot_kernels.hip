@@ -48,6 +48,8 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
     __shared__ PoseEval s_pe[kMaxG];
     __shared__ PriorTerms s_pri[kMaxG];
     __shared__ FrameDev s_f;
+    __shared__ unsigned s_keep;
+    __shared__ int s_pos;
     // one block per tile: the tile's own mask (lane hh < nh of each wave reads
     // the level of hypothesis hb + hh) also covers a level with no hypothesis
     // left, so the run flag is not read here.  By default the levels, the LM
@@ -59,11 +61,21 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
     const TileItem ti = e.tiles[blockIdx.x];
     const FrameDev *f = e.frames + ti.frame;
     const int G = e.G;
-    const int h0 = ti.htile * G;
     const int hb = ti.hbase;
-    const int nh = ti.nh;
+    // With packed lists (e.phs) the tiling of this frame in this pass is the
+    // pass kernel's (use_packed on the same count): packed, slot hh is packed
+    // entry hb + hh, the first nh slots still at the level; otherwise
+    // hypothesis hb + hh.  Either way the survivors are appended to the next
+    // pass's lists.
+    const bool lists = e.phs != nullptr;
+    const int cnt = lists ? e.pcount[ti.frame] : 0;
+    const bool packed = lists && use_packed(cnt, f->M, G, ti.n_ptiles, e.pack_min);
+    const int nh = packed ? min(ti.nh, cnt - ti.htile * G) : ti.nh;
+    if (packed && nh <= 0) return;               // past the hypotheses still at the level
+    const HypState *hs_in = (packed ? e.phs : e.hs) + hb;
+    const PoseEval *pe_in = (packed ? e.ppose : e.pose) + hb;
     const int lane = threadIdx.x & 63;
-    const int lv = lane < nh ? e.hlev[hb + lane] : -1;
+    const int lv = lane < nh ? (packed ? e.level : e.hlev[hb + lane]) : -1;
     if (e.mask_first && __builtin_amdgcn_readfirstlane((unsigned)__ballot(lv == e.level)) == 0) return;
     // LM states and poses of the tile's hypotheses and the frame's constants,
     // fetched by the summing threads and staged in LDS (the LM step then reads
@@ -85,7 +97,7 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
         // unused: the DSM lookup clamps to the grid whatever the pose)
         const int hh = threadIdx.x - kEpiThreads;
         if (lm_mode && hh < nh) {
-            const HypState &hs = e.hs[hb + hh];
+            const HypState &hs = hs_in[hh];
             const bool start = hs.phase == PHASE_START;
             double Tp[12];
 #pragma unroll
@@ -93,20 +105,18 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
                 const double a = hs.T[i], c = hs.Tc[i];
                 Tp[i] = start ? a : c;
             }
-            PriorTerms p;
+            PriorTerms p{};
             prior_terms(*f, Tp, p);
             s_pri[hh] = p;
         }
     } else {
-        const double *hs_src = reinterpret_cast<const double *>(e.hs + hb);
-        const double *pe_src = reinterpret_cast<const double *>(e.pose + hb);
         double hsv[3], pev = 0.0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int w = threadIdx.x + k * kEpiThreads;
-            hsv[k] = w < nhs ? hs_src[w] : 0.0;
+            hsv[k] = w < nhs ? reinterpret_cast<const double *>(hs_in)[w] : 0.0;
         }
-        if ((int)threadIdx.x < npe) pev = pe_src[threadIdx.x];
+        if ((int)threadIdx.x < npe) pev = reinterpret_cast<const double *>(pe_in)[threadIdx.x];
         unsigned long long fdv = 0;
         if (threadIdx.x < kFdW) fdv = reinterpret_cast<const unsigned long long *>(f)[threadIdx.x];
         // The tile's records are read as float4 columns (4 adjacent values; a
@@ -181,8 +191,8 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
     if (threadIdx.x == kEpiThreads)   // the prior wave: not on an LM thread's path
         atomicAdd(e.pairs, (unsigned long long)__popc(act) * (unsigned long long)s_f.lv[e.level].N);
     const int t = threadIdx.x;
-    const int gh = hb + t;
-    const int m = h0 + t;
+    const int gh = (packed && t < nh) ? s_hs[t].home : hb + t;
+    const int m = gh - f->hyp_base;
     const double *S = s_sum[t];
     if (!lm_mode) {
         if (t >= G || !((act >> t) & 1u)) return;
@@ -200,22 +210,47 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
     }
     // the LM state lives in LDS while it is updated (a register copy of the
     // whole state would not fit beside the reduction's registers)
+    bool stay = false;
     if (t < G && ((act >> t) & 1u)) {
         int hl = e.level;
         lm_advance(s_f, s_hs[t], S, s_pri[t], s_pe[t], hl);
         e.hlev[gh] = hl;
-        if (e.next_flag && hl == e.level) *e.next_flag = 1;   // the next pass of this level has work
+        stay = hl == e.level;
+        if (e.next_flag && stay) *e.next_flag = 1;   // the next pass of this level has work
+    }
+    if (lists) {
+        // hypotheses that stay at the level go to the next pass's packed list:
+        // one atomic per tile reserves their entries (slot order within the tile)
+        const unsigned keep = (unsigned)__ballot(stay);          // t < G <= 16: wave 0 only
+        if (threadIdx.x == 0) {
+            s_keep = keep;
+            s_pos = keep ? atomicAdd(e.pcount_next + ti.frame, __popc(keep)) : 0;
+        }
     }
     __syncthreads();
     // write the updated states back with the whole block (active hypotheses only)
     {
-        double *hs_dst = reinterpret_cast<double *>(e.hs + hb);
-        double *pe_dst = reinterpret_cast<double *>(e.pose + hb);
         const double *hs_lds = reinterpret_cast<const double *>(s_hs);
         const double *pe_lds = reinterpret_cast<const double *>(s_pe);
+        auto home = [&](int hh) -> int { return packed ? s_hs[hh].home : hb + hh; };
         for (int w = threadIdx.x; w < nhs; w += kEpiBlock)
-            if ((act >> (w / kHsW)) & 1u) hs_dst[w] = hs_lds[w];
-        if ((int)threadIdx.x < npe && ((act >> (threadIdx.x / kPeW)) & 1u)) pe_dst[threadIdx.x] = pe_lds[threadIdx.x];
+            if ((act >> (w / kHsW)) & 1u) reinterpret_cast<double *>(e.hs + home(w / kHsW))[w % kHsW] = hs_lds[w];
+        if ((int)threadIdx.x < npe && ((act >> (threadIdx.x / kPeW)) & 1u))
+            reinterpret_cast<double *>(e.pose + home(threadIdx.x / kPeW))[threadIdx.x % kPeW] = pe_lds[threadIdx.x];
+        if (lists) {
+            // the survivors' states and next poses, to their entries of the next list
+            const unsigned keep = s_keep;
+            const int dst0 = f->hyp_base + s_pos;
+            constexpr int kW = kHsW + kPeW;
+            for (int w = threadIdx.x; w < __popc(keep) * kW; w += kEpiBlock) {
+                const int r = w / kW, x = w - r * kW;
+                int j = 0;
+                for (int seen = 0; j < kMaxG; ++j)
+                    if (((keep >> j) & 1u) && seen++ == r) break;
+                if (x < kHsW) reinterpret_cast<double *>(e.phs_next + dst0 + r)[x] = hs_lds[j * kHsW + x];
+                else reinterpret_cast<double *>(e.ppose_next + dst0 + r)[x - kHsW] = pe_lds[j * kPeW + x - kHsW];
+            }
+        }
     }
 }
 
@@ -267,7 +302,7 @@ __global__ __launch_bounds__(256) void init_kernel(const FrameDev *frames, HypSt
     } else {
         for (int i = 0; i < 12; ++i) src[i] = f.poses_in[(size_t)12 * m + i];
     }
-    HypState s;
+    HypState s{};
     bool finite = true;
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
@@ -291,9 +326,10 @@ __global__ __launch_bounds__(256) void init_kernel(const FrameDev *frames, HypSt
     s.it_level = s.it_total = 0;
     s.status = finite ? ST_MAX_ITERS : ST_DEGENERATE;
     s.nvalid = 0;
-    s.pad0 = s.pad1 = 0;
+    s.home = gh;
+    s.pad1 = 0;
     hs[gh] = s;
-    PoseEval p;
+    PoseEval p{};
 #pragma unroll
     for (int i = 0; i < 12; ++i) p.v[i] = src[i];
 #pragma unroll
@@ -634,6 +670,86 @@ hipError_t launch_finalize(const FrameDev *frames, int n_frames, const HypState 
                            hipStream_t s)
 {
     hipLaunchKernelGGL(finalize_kernel, dim3(n_frames), dim3(256), 0, s, frames, hs, hlev);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ packing
+// The LM states and poses under evaluation of each frame's hypotheses whose
+// pending level is `level`, in index order, to phs / ppose[hyp_base + 0 ..
+// count), count to pcount[frame], and the frame's counts in pclear0 and
+// pclear1 (the next two passes' append targets) cleared.  Block (c, frame)
+// takes hypotheses 16 c .. 16 c + 15: it counts the listed ones before its
+// chunk (the hypotheses' level words, a block-wide sum) for the chunk's first
+// entry, then copies the chunk's records a word per thread.  Block (0, frame)
+// also counts the whole frame.
+constexpr int kPackChunk = 16;
+constexpr int kPackBlock = 256;
+
+__device__ __forceinline__ int block_count(const int *hlev, int lo, int hi, int level, int *s_red)
+{
+    int c = 0;
+    for (int m = lo + (int)threadIdx.x; m < hi; m += kPackBlock) c += hlev[m] == level;
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    int t = 0;
+    for (int w = 0; w < kPackBlock / 64; ++w) t += s_red[w];
+    return t;
+}
+
+__global__ __launch_bounds__(kPackBlock) void pack_kernel(const FrameDev *frames, const int *hlev, int level,
+                                                          const HypState *hs, const PoseEval *pose, HypState *phs,
+                                                          PoseEval *ppose, int *pcount, int *pclear0, int *pclear1)
+{
+    __shared__ int s_red[kPackBlock / 64];
+    __shared__ int s_src[kPackChunk];
+    constexpr int kHsW = sizeof(HypState) / sizeof(double), kPeW = sizeof(PoseEval) / sizeof(double);
+    constexpr int kW = kHsW + kPeW;
+    const FrameDev &f = frames[blockIdx.y];
+    const int m0 = blockIdx.x * kPackChunk;
+    if (m0 >= f.M) return;
+    const int b = f.hyp_base;
+    const int before = block_count(hlev, b, b + m0, level, s_red);
+    if (blockIdx.x == 0) {
+        const int total = block_count(hlev, b, b + f.M, level, s_red);
+        if (threadIdx.x == 0) {
+            pcount[blockIdx.y] = total;
+            pclear0[blockIdx.y] = 0;
+            pclear1[blockIdx.y] = 0;
+        }
+    }
+    // the chunk's listed hypotheses, in order (lanes 0..15 of wave 0)
+    int n = 0;
+    if (threadIdx.x < 64) {
+        const int m = m0 + (int)threadIdx.x;
+        const bool in = threadIdx.x < kPackChunk && m < f.M && hlev[b + m] == level;
+        const unsigned long long bal = __ballot(in);
+        if (in) s_src[__popcll(bal & ((1ull << threadIdx.x) - 1ull))] = b + m;
+        n = __popcll(bal);
+        if (threadIdx.x == 0) s_red[0] = n;
+    }
+    __syncthreads();
+    n = s_red[0];
+    const int dst0 = b + before;
+    for (int w = threadIdx.x; w < n * kW; w += kPackBlock) {
+        const int r = w / kW, x = w - r * kW;
+        if (x < kHsW)
+            reinterpret_cast<double *>(phs + dst0 + r)[x] = reinterpret_cast<const double *>(hs + s_src[r])[x];
+        else
+            reinterpret_cast<double *>(ppose + dst0 + r)[x - kHsW] =
+                reinterpret_cast<const double *>(pose + s_src[r])[x - kHsW];
+    }
+}
+
+hipError_t launch_pack(const FrameDev *frames, int n_frames, int max_M, const int *hlev, int level,
+                       const HypState *hs, const PoseEval *pose, HypState *phs, PoseEval *ppose, int *pcount,
+                       int *pclear0, int *pclear1, hipStream_t s)
+{
+    if (n_frames <= 0 || max_M <= 0) return hipSuccess;
+    const dim3 grid((max_M + kPackChunk - 1) / kPackChunk, n_frames);
+    hipLaunchKernelGGL(pack_kernel, grid, dim3(kPackBlock), 0, s, frames, hlev, level, hs, pose, phs, ppose, pcount,
+                       pclear0, pclear1);
     return hipGetLastError();
 }
 

@@ -287,7 +287,7 @@ __device__ inline void add_priors(const FrameDev &f, const PriorTerms &p, double
 __device__ inline void add_priors(const FrameDev &f, const double T[12], double ag, double ar, double H[21],
                                   double g[6], double &cost)
 {
-    PriorTerms p;
+    PriorTerms p{};
     prior_terms(f, T, p);
     add_priors(f, p, ag, ar, H, g, cost);
 }

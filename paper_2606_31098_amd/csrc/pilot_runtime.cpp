@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -46,12 +47,12 @@ struct DevBuf {
 };
 
 struct LaunchGroup {
-    int level, C, dtype;
+    int level = 0, C = 0, dtype = 0;
     TileConfig tc{};
-    int item_off, n_items;
-    int tile_off, n_tiles;
-    int passes;
-    int stat_class;
+    int item_off = 0, n_items = 0;
+    int tile_off = 0, n_tiles = 0;
+    int passes = 0;
+    int stat_class = 0;
 };
 
 struct Plan {
@@ -62,11 +63,11 @@ struct Plan {
     int total_hyps = 0, max_M = 0, max_levels = 0;
     size_t partial_floats = 0;
     std::string key;
-    // Gram tables of the (frame, level) pairs whose tiles use a Gram pass variant (3 to 8)
+    // Gram tables of the (frame, level) pairs whose tiles use a Gram pass variant (3 to 10)
     struct GramJob {
-        int frame, level;
-        size_t offset;
-        int fmt;
+        int frame = 0, level = 0;
+        size_t offset = 0;
+        int fmt = 0;
     };
     std::vector<GramJob> gram_jobs;
     size_t gram_bytes = 0;
@@ -74,8 +75,8 @@ struct Plan {
 };
 
 struct TimedLaunch {
-    hipEvent_t a, b;
-    int level, cls;
+    hipEvent_t a = nullptr, b = nullptr;
+    int level = 0, cls = 0;
 };
 
 struct ServingSlot {
@@ -105,7 +106,7 @@ struct pilot_ctx {
     std::string err;
 
     // workspace
-    DevBuf desc, hs, pose, hlev, partials, pairs, gram, passflag;
+    DevBuf desc, hs, pose, hlev, partials, pairs, gram, passflag, phs, ppose, pcount;
     size_t ws_bytes = 0;
     unsigned generation = 0;
     // the bytes of the last descriptor upload and the workspace generation
@@ -525,12 +526,12 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
         if (only_level >= 0 && l != only_level) continue;
         // each frame's tiles depend on its own shape only, so its sums (and
         // results) are the same alone or batched with any other frames
-        std::map<std::array<int, 5>, std::vector<int>> by_class;
+        std::map<std::array<int, 6>, std::vector<int>> by_class;
         for (int i = 0; i < n; ++i)
             if (l < frames[i].n_levels) {
                 const pilot_level &L = frames[i].level[l];
                 const TileConfig tc = choose_tile(ctx, L.C, L.dtype, L.N, frames[i].M, (long)L.H * L.W);
-                by_class[{L.C, L.dtype, tc.G, tc.PPG, tc.variant}].push_back(i);
+                by_class[{L.C, L.dtype, tc.G, tc.PPG, tc.variant, tc.pack}].push_back(i);
             }
         for (auto &kv : by_class) {
             LaunchGroup g{};
@@ -573,7 +574,7 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
             plan.partial_floats = std::max(plan.partial_floats, (size_t)g.n_items * g.tc.G * kNV);
             plan.groups.push_back(g);
             key << "|l" << l << "c" << g.C << "d" << g.dtype << "G" << g.tc.G << "p" << g.tc.PPG << "g" << g.tc.grid
-                << "v" << g.tc.variant << "i" << g.n_items << "t" << g.n_tiles << "s" << g.passes;
+                << "v" << g.tc.variant << "k" << g.tc.pack << "i" << g.n_items << "t" << g.n_tiles << "s" << g.passes;
         }
     }
     plan.key = key.str();
@@ -592,9 +593,9 @@ hipEvent_t pool_event(pilot_ctx *ctx)
 }
 
 struct DevPtrs {
-    FrameDev *frames;
-    WorkItem *items;
-    TileItem *tiles;
+    FrameDev *frames = nullptr;
+    WorkItem *items = nullptr;
+    TileItem *tiles = nullptr;
 };
 
 // Device workspace a schedule runs on: the context's buffers, or the fixed
@@ -606,6 +607,14 @@ struct Ws {
     float *partials = nullptr;
     unsigned long long *pairs = nullptr;
     int *passflag = nullptr;
+    // packed hypothesis tiles, three rotating buffers (pass k of a level reads
+    // buffer k % 3, its epilogue appends to (k + 1) % 3, and the pass clears the
+    // counts of (k + 2) % 3): per frame the LM states of the hypotheses still at
+    // the level, their poses under evaluation and their number
+    HypState *phs = nullptr;     // 3 x hyps
+    PoseEval *ppose = nullptr;   // 3 x hyps
+    int *pcount = nullptr;       // 3 x frames
+    int hyps = 0, frames = 0;    // buffer strides
 };
 
 Ws ws_of(const pilot_ctx *ctx)
@@ -617,6 +626,9 @@ Ws ws_of(const pilot_ctx *ctx)
     w.partials = (float *)ctx->partials.p;
     w.pairs = (unsigned long long *)ctx->pairs.p;
     w.passflag = (int *)ctx->passflag.p;
+    w.phs = (HypState *)ctx->phs.p;
+    w.ppose = (PoseEval *)ctx->ppose.p;
+    w.pcount = (int *)ctx->pcount.p;
     return w;
 }
 
@@ -673,14 +685,21 @@ int ensure_state(pilot_ctx *ctx, Plan &plan)
     if ((rc = ensure(ctx, ctx->partials, std::max<size_t>(1, plan.partial_floats) * sizeof(float)))) return rc;
     if ((rc = ensure(ctx, ctx->pairs, kStatClasses * sizeof(unsigned long long), true))) return rc;
     if ((rc = ensure(ctx, ctx->passflag, (size_t)PILOT_MAX_LEVELS * plan.flag_stride * sizeof(int)))) return rc;
+    if ((rc = ensure(ctx, ctx->phs, 3 * H * sizeof(HypState)))) return rc;
+    if ((rc = ensure(ctx, ctx->ppose, 3 * H * sizeof(PoseEval)))) return rc;
+    if ((rc = ensure(ctx, ctx->pcount, 3 * std::max<size_t>(1, plan.frames.size()) * sizeof(int)))) return rc;
     return PILOT_OK;
 }
 
 // Enqueue one pass (pass kernel + epilogue) of a launch group.
+// packed: the Gram-table variants (3 to 10) walk packed hypothesis tiles,
+// built by the pack kernel right before the pass.
 int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Ws &ws, const LaunchGroup &g, int mode,
                  hipStream_t s, bool timed, const int *run_flag = nullptr, int *next_flag = nullptr,
-                 bool mask_first = false)
+                 bool mask_first = false, bool packed = false, int pass_index = 0)
 {
+    packed = packed && uses_gram(g.tc) && g.tc.pack != 0;
+    const int b0 = pass_index % 3, b1 = (pass_index + 1) % 3, b2 = (pass_index + 2) % 3;
     if (uses_gram(g.tc))                       // every frame of the group needs its Gram table
         for (int t = g.tile_off; t < g.tile_off + g.n_tiles; ++t)
             if (!plan.frames[plan.tiles[t].frame].lv[g.level].gram)
@@ -694,6 +713,13 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Ws &
     a.hlev = ws.hlev;
     a.partials = ws.partials;
     a.run_flag = run_flag;
+    if (packed) {
+        a.ppose = ws.ppose + (size_t)b0 * ws.hyps;
+        a.pcount = ws.pcount + (size_t)b0 * ws.frames;
+        a.pcount_clear = ws.pcount + (size_t)b2 * ws.frames;
+        a.n_frames = ws.frames;
+        a.pack_min = g.tc.pack == 2 ? 0 : 4 * ctx->ncu;
+    }
     TimedLaunch tl{};
     if (timed) {
         tl.a = pool_event(ctx);
@@ -722,6 +748,15 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Ws &
     e.pairs = ws.pairs + g.stat_class;
     e.next_flag = next_flag;
     e.mask_first = mask_first ? 1 : 0;
+    if (packed) {
+        e.phs = ws.phs + (size_t)b0 * ws.hyps;
+        e.ppose = ws.ppose + (size_t)b0 * ws.hyps;
+        e.pcount = ws.pcount + (size_t)b0 * ws.frames;
+        e.phs_next = ws.phs + (size_t)b1 * ws.hyps;
+        e.ppose_next = ws.ppose + (size_t)b1 * ws.hyps;
+        e.pcount_next = ws.pcount + (size_t)b1 * ws.frames;
+        e.pack_min = a.pack_min;
+    }
     HIPCHK(ctx, launch_epilogue(e, s));
     ctx->launches[g.stat_class]++;
     return PILOT_OK;
@@ -745,22 +780,43 @@ int enqueue_schedule(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const 
     if (int rc = enqueue_gram(ctx, plan, dp, s)) return rc;
     HIPCHK(ctx, launch_init(dp.frames, (int)plan.frames.size(), plan.max_M, ws.hs, ws.pose, ws.hlev, MODE_LM,
                             nullptr, 0, s, ws.passflag, PILOT_MAX_LEVELS * plan.flag_stride, plan.flag_stride));
+    // packed hypothesis tiles: the Gram-variant passes walk, G at a time, the
+    // list of each frame's hypotheses still at the level (listed in index order
+    // at the level's start, then by each epilogue, which appends the ones that
+    // stay), so a pass costs what its live hypotheses need rather than every
+    // tile that still holds one.  Sums do not depend on a hypothesis' tile or
+    // slot, so results are those of contiguous tiles, bit for bit.
+    const int nf = (int)plan.frames.size();
+    bool pack = false;
+    for (const LaunchGroup &g : plan.groups) pack = pack || (uses_gram(g.tc) && g.tc.pack != 0);
+    Ws wp = ws;
+    wp.hyps = std::max(1, plan.total_hyps);
+    wp.frames = std::max(1, nf);
+    // a level's first pass reads buffer 0, filled here; its epilogue appends
+    // to buffer 1, and the next pass clears buffer 2
+    auto pack_level = [&](int level) -> hipError_t {
+        return launch_pack(dp.frames, nf, plan.max_M, wp.hlev, level, wp.hs, wp.pose, wp.phs, wp.ppose, wp.pcount,
+                           wp.pcount + wp.frames, wp.pcount + 2 * (size_t)wp.frames, s);
+    };
+    if (pack) HIPCHK(ctx, pack_level(0));
     for (int l = 0; l < plan.max_levels; ++l) {
         int maxp = 0;
         for (const LaunchGroup &g : plan.groups)
             if (g.level == l) maxp = std::max(maxp, g.passes);
-        for (int k = 0; k < maxp; ++k)
+        bool prunes = false;
+        for (const FrameDev &f : plan.frames) prunes = prunes || (f.keep_top > 0 && f.prune_level == l);
+        for (int k = 0; k < maxp; ++k) {
             for (const LaunchGroup &g : plan.groups)
                 if (g.level == l && k < g.passes) {
                     // pass k of level l runs only if pass k - 1 left a hypothesis at level l
                     int *flags = ws.passflag + (size_t)l * plan.flag_stride;
-                    int rc = enqueue_pass(ctx, plan, dp, ws, g, MODE_LM, s, timed, flags + k, flags + k + 1);
+                    int rc = enqueue_pass(ctx, plan, dp, wp, g, MODE_LM, s, timed, flags + k, flags + k + 1, false,
+                                          pack, k);
                     if (rc) return rc;
                 }
-        bool prunes = false;
-        for (const FrameDev &f : plan.frames) prunes = prunes || (f.keep_top > 0 && f.prune_level == l);
-        if (prunes)
-            HIPCHK(ctx, launch_prune(dp.frames, (int)plan.frames.size(), ws.hs, ws.pose, ws.hlev, s));
+        }
+        if (prunes) HIPCHK(ctx, launch_prune(dp.frames, nf, ws.hs, ws.pose, ws.hlev, s));
+        if (pack && l + 1 < plan.max_levels) HIPCHK(ctx, pack_level(l + 1));
     }
     HIPCHK(ctx, launch_finalize(dp.frames, (int)plan.frames.size(), ws.hs, ws.hlev, s));
     return PILOT_OK;
@@ -770,12 +826,18 @@ void load_tune_cache(pilot_ctx *ctx)
 {
     if (ctx->tune_cache.empty()) return;
     std::ifstream in(ctx->tune_cache);
-    std::string key;
-    TileConfig tc{};
-    while (in >> key >> tc.G >> tc.PPG >> tc.grid >> tc.variant)
+    std::string line;
+    // "key G PPG grid variant [pack]" per line (pack 0 when absent)
+    while (std::getline(in, line)) {
+        std::istringstream ls(line);
+        std::string key;
+        TileConfig tc{};
+        if (!(ls >> key >> tc.G >> tc.PPG >> tc.grid >> tc.variant)) continue;
+        if (!(ls >> tc.pack)) tc.pack = 0;
         if ((tc.G == 1 || tc.G == 2 || tc.G == 4 || tc.G == 8 || tc.G == 16) && tc.PPG >= 1 && tc.PPG <= 64 &&
-            tc.variant >= 1 && tc.variant <= 10)
+            tc.variant >= 1 && tc.variant <= 10 && tc.pack >= 0 && tc.pack <= 2)
             ctx->tuned[key] = tc;
+    }
 }
 
 int collect_timings(pilot_ctx *ctx)
@@ -877,6 +939,7 @@ void pilot_destroy(pilot_ctx *ctx)
         if (s.p) hipHostFree(s.p);
     }
     for (DevBuf *b : {&ctx->desc, &ctx->hs, &ctx->pose, &ctx->hlev, &ctx->partials, &ctx->pairs, &ctx->gram,
+                      &ctx->passflag, &ctx->phs, &ctx->ppose, &ctx->pcount,
                       &ctx->s_frames, &ctx->s_desc, &ctx->s_done})
         if (b->p) hipFree(b->p);
     for (auto &fb : ctx->flagbuf) {
@@ -1008,6 +1071,12 @@ int pilot_solve_static(pilot_ctx *ctx, const pilot_frame *frames, int n_frames, 
     off += align256(kStatClasses * sizeof(unsigned long long));
     const size_t o_flag = off;
     off += align256((size_t)PILOT_MAX_LEVELS * plan.flag_stride * sizeof(int));
+    const size_t o_phs = off;
+    off += align256(3 * H * sizeof(HypState));
+    const size_t o_ppose = off;
+    off += align256(3 * H * sizeof(PoseEval));
+    const size_t o_pcount = off;
+    off += align256(3 * std::max<size_t>(1, plan.frames.size()) * sizeof(int));
     if (off > static_scratch_bytes())
         return fail(ctx, PILOT_ENOMEM,
                     "pilot_solve_static: these frames need %zu bytes of device scratch; the fixed scratch holds %zu "
@@ -1026,6 +1095,9 @@ int pilot_solve_static(pilot_ctx *ctx, const pilot_frame *frames, int n_frames, 
     ws.partials = (float *)(base + o_part);
     ws.pairs = (unsigned long long *)(base + o_pairs);
     ws.passflag = (int *)(base + o_flag);
+    ws.phs = (HypState *)(base + o_phs);
+    ws.ppose = (PoseEval *)(base + o_ppose);
+    ws.pcount = (int *)(base + o_pcount);
 
     // descriptors: from a host image the context keeps (pageable; the copy
     // has consumed it when hipMemcpyAsync returns)
@@ -1218,14 +1290,25 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
         if (rc) break;
         for (size_t c = 0; c < cand.size() && rc == PILOT_OK; ++c) rc = run(c);
         if (rc) break;
-        // second round for the 8 best of each key
-        std::vector<char> again(cand.size(), 0);
+        // second round for the 8 best of each key, and the same tiles with packed
+        // hypothesis tiles (Gram variants; packing pays where stragglers are many)
+        const size_t n1 = cand.size();
+        std::vector<char> again(n1, 0);
         for (size_t k = 0; k < todo.size(); ++k) {
-            std::vector<size_t> order(cand.size());
-            for (size_t c = 0; c < cand.size(); ++c) order[c] = c;
+            std::vector<size_t> order(n1);
+            for (size_t c = 0; c < n1; ++c) order[c] = c;
             std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return score[a][k] < score[b][k]; });
             for (size_t i = 0; i < 8 && i < order.size(); ++i) again[order[i]] = 1;
         }
+        for (size_t c = 0; c < n1; ++c)
+            if (again[c] && uses_gram(cand[c]))
+                for (int pk : {1, 2}) {
+                    TileConfig t = cand[c];
+                    t.pack = pk;
+                    cand.push_back(t);
+                    score.push_back(std::vector<double>(todo.size(), 1e300));
+                    again.push_back(1);
+                }
         for (size_t c = 0; c < cand.size() && rc == PILOT_OK; ++c)
             if (again[c]) rc = run(c);
     } while (false);
@@ -1246,7 +1329,7 @@ int pilot_autotune(pilot_ctx *ctx, const pilot_frame *frame)
         if (!ctx->tune_cache.empty()) {
             std::ofstream out(ctx->tune_cache, std::ios::app);
             out << todo[k] << " " << cand[bi].G << " " << cand[bi].PPG << " " << cand[bi].grid << " "
-                << cand[bi].variant << "\n";
+                << cand[bi].variant << " " << cand[bi].pack << "\n";
         }
     }
     return PILOT_OK;
@@ -1257,7 +1340,7 @@ int pilot_tile_choice(pilot_ctx *ctx, int C, int dtype, int N, int M, int64_t HW
     if (!ctx || !buf || buflen < 1) return fail(ctx, PILOT_EINVAL, "ctx/buf: invalid");
     TileConfig tc = choose_tile(ctx, C, dtype, N, M, (long)HW);
     auto it = ctx->tuned.find(tune_key(C, dtype, N, M, (long)HW));
-    snprintf(buf, buflen, "G=%d PPG=%d BPC=%d V=%d tuned=%d", tc.G, tc.PPG, tc.grid, tc.variant,
+    snprintf(buf, buflen, "G=%d PPG=%d BPC=%d V=%d pack=%d tuned=%d", tc.G, tc.PPG, tc.grid, tc.variant, tc.pack,
              (int)(it != ctx->tuned.end() && tile_ok(it->second, C, dtype)));
     return PILOT_OK;
 }
@@ -1393,12 +1476,12 @@ int serving_rebuild(pilot_ctx *ctx)
             slot_of.push_back(i);
         }
     for (int l = 0; l < PILOT_MAX_LEVELS; ++l) {
-        std::map<std::array<int, 5>, std::vector<int>> by_class;
+        std::map<std::array<int, 6>, std::vector<int>> by_class;
         for (int k = 0; k < (int)frames.size(); ++k)
             if (l < frames[k].n_levels) {
                 const pilot_level &L = frames[k].level[l];
                 const TileConfig tc = serving_tile(ctx, L.C, L.dtype, L.N, frames[k].M, (long)L.H * L.W);
-                by_class[{L.C, L.dtype, tc.G, tc.PPG, tc.variant}].push_back(k);
+                by_class[{L.C, L.dtype, tc.G, tc.PPG, tc.variant, tc.pack}].push_back(k);
             }
         for (auto &kv : by_class) {
             LaunchGroup g{};

@@ -264,6 +264,45 @@ def test_narrow_lane_groups_match_oracle(tmp_path, variant, G):
     c.close()
 
 
+@pytest.mark.parametrize("dtype,variant,G", [("f32", 3, 4), ("f32", 4, 8), ("bf16", 5, 8), ("bf16", 9, 4),
+                                             ("bf16", 10, 2), ("bf16", 8, 16)])
+def test_packed_hypothesis_tiles_leave_results_bitwise_unchanged(tmp_path, dtype, variant, G):
+    """Packed hypothesis tiles (the hypotheses still at a level walked G at a
+    time, in lists rebuilt every pass) against contiguous tiles: a hypothesis'
+    sums do not depend on its tile or slot, so a batch of two frames of
+    uneven M gives bitwise the same poses, costs, iterations, statuses and
+    selection with packing off (0), when it saves rounds of blocks (1) and
+    always (2)."""
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    d = 0 if dtype == "f32" else 1
+    fr = [pyramid_frame(seed=21, N=900, M=37, iters=(6, 6, 6)), pyramid_frame(seed=22, N=700, M=13, iters=(5, 7, 4))]
+    if dtype == "bf16":
+        fr = [bf16_copy(f) for f in fr]
+    outs = []
+    for pack in (0, 1, 2):
+        cache = tmp_path / f"tune{pack}.txt"
+        with open(cache, "w") as fh:
+            for f in fr:
+                for L in f.levels:
+                    g = G if (G >= 4 or L.C <= (32 if G == 1 else 64)) else 4
+                    fh.write(f"C{L.C}_d{d}_N{_floor_log2(L.N)}_M{_floor_log2(f.M)}_P{_floor_log2(L.H * L.W)}_v3 "
+                             f"{g} 2 0 {variant} {pack}\n")
+        c = Context(0, tune_cache=str(cache))
+        L0 = fr[0].levels[0]
+        assert f"pack={pack}" in c.tile_choice(L0.C, d, L0.N, fr[0].M, L0.H * L0.W)
+        say(f"packed tiles: dtype={dtype} variant={variant} G={G} pack={pack}")
+        res = c.solve([DeviceFrame(f, dtype=dtype) for f in fr])
+        torch.cuda.synchronize()
+        outs.append([r.numpy() for r in res])
+        c.close()
+    for pack in (1, 2):
+        for i in range(2):
+            a, b = outs[0][i], outs[pack][i]
+            for k in ("poses", "cost", "iterations", "status"):
+                assert np.array_equal(a[k], b[k]), (pack, i, k)
+            assert a["best"] == b["best"], (pack, i)
+
+
 @pytest.mark.parametrize("scale", [1e-9, 1e-6, 1e-3, 1.0, 1e3, 1e6, 1e9])
 def test_cauchy_loss_per_pair_matches_oracle(ctx, scale):
     """The Cauchy loss of a pair (its log(1 + q) comes from a short atanh

@@ -369,8 +369,10 @@ def test_autotune_writes_every_level_key_and_stays_correct(tmp_path):
             f"_P{int(math.floor(math.log2(L.H * L.W)))}_v3" for L in f.levels}
     assert {ln[0] for ln in lines} == keys and len(lines) == len(keys)
     for ln in lines:
-        G, ppg, bpc, var = map(int, ln[1:])
-        assert G in (4, 8, 16) and ppg in (2, 4, 8, 16) and bpc in (0, 2, 4) and var in (1, 2, 3, 4, 5, 6, 7, 8)
+        G, ppg, bpc, var, pack = map(int, ln[1:])
+        # f32 maps: the variants that read f32 maps, lane groups of 4 to 16
+        assert G in (4, 8, 16) and ppg in (2, 4, 8, 16) and bpc in (0, 2, 4) and var in (1, 2, 3, 4, 7)
+        assert pack in (0, 1, 2) and (pack == 0 or var >= 3)
     ctx2 = Context(0, tune_cache=str(cache))
     for L in f.levels:
         assert "tuned=1" in ctx2.tile_choice(L.C, 0, L.N, f.M, L.H * L.W)
