@@ -62,7 +62,10 @@ def parse():
                    help="tile database (read; shapes missing from it are tuned and appended)")
     p.add_argument("--write-tiles", action="store_true",
                    help="only tune the tiles of every workload shape into --tune-cache")
-    p.add_argument("--serve-seconds", type=float, default=20.0, help="config 5: simulated duration")
+    p.add_argument("--serve-seconds", type=float, default=60.0, help="config 5: simulated duration")
+    p.add_argument("--serve-trace", default=None, metavar="PATH",
+                   help="config 5: write one JSON line per served frame (stream, sizes, arrival, admission, "
+                        "completion, passes) to PATH")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="only run 5 plain device copies of MIB MiB (scale for the DRAM byte counters)")
     return p.parse_args()
@@ -532,6 +535,13 @@ def run_serving_config(args, worlds):
     st = loop.run(reqs, realtime=True, on_complete=on_complete)
     counters = ctx.stats(reset=True)
     lat = [c.latency * 1e3 for c in st.completions]
+    if args.serve_trace:
+        with open(args.serve_trace, "w") as fh:
+            for c in st.completions:
+                spec = c.request.tag
+                fh.write(json.dumps({"stream": spec.seq, "index": spec.index, "N": int(spec.P.shape[0]),
+                                     "M": int(spec.offsets.shape[0]), "arrival": c.request.t_arrival,
+                                     "admit": c.t_admit, "done": c.t_done, "passes": c.steps}) + "\n")
     bp = best_poses[:len(order)].cpu().numpy()
     te, re_ = [], []
     for k, spec in order.items():

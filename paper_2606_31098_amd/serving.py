@@ -17,6 +17,7 @@ host.
 from __future__ import annotations
 
 import collections
+import gc
 import time
 from dataclasses import dataclass, field
 from typing import Any, Callable, Dict, List, Optional
@@ -66,7 +67,23 @@ class ServingLoop:
         self.clock = clock
 
     def run(self, requests: List[Request], realtime: bool = True,
-            on_complete: Optional[Callable[[Completion], None]] = None) -> RunStats:
+            on_complete: Optional[Callable[[Completion], None]] = None, pause_gc: bool = True) -> RunStats:
+        """Serve `requests` (see the module docstring).  pause_gc: Python's
+        cyclic garbage collector is switched off for the run (a full
+        collection over the many live request objects stalls the loop for
+        tens of milliseconds, every frame in flight then waiting on it) and
+        restored afterwards."""
+        was_enabled = gc.isenabled()
+        if pause_gc:
+            gc.collect()
+            gc.disable()
+        try:
+            return self._run(requests, realtime, on_complete)
+        finally:
+            if pause_gc and was_enabled:
+                gc.enable()
+
+    def _run(self, requests, realtime, on_complete) -> RunStats:
         reqs = sorted(requests, key=lambda r: r.t_arrival)
         st = RunStats(last_arrival=reqs[-1].t_arrival if reqs else 0.0)
         queues: Dict[int, collections.deque] = collections.defaultdict(collections.deque)

@@ -330,6 +330,38 @@ def test_cauchy_loss_per_pair_matches_oracle(ctx, scale):
             assert abs(cost[m] - co) <= 1e-12 * abs(co), (lvl, m, cost[m], co)
 
 
+@pytest.mark.parametrize("scale", [1e-9, 1e-6, 1e-3, 1.0, 1e3, 1e6, 1e9])
+def test_fp32_cauchy_loss_per_pair_matches_oracle(tmp_path, scale):
+    """The same sweep through the FP32 per-pair path (variant 10 on bf16 maps,
+    whose log(1 + q) is the hardware logarithm with the log1p correction
+    q / (u - 1)): the cost of each hypothesis within the bf16 bar (1e-5
+    relative) of the oracle's on the same rounded inputs, from q ~ 1e-8 to 1e10."""
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    f = bf16_copy(S.make_frame(2, 0, noise=True, N=4, M=8, level_shapes=((30, 40, 16), (60, 80, 32), (120, 160, 64)),
+                               iters=(6, 6, 6), dsm_side=128, seed=5))
+    for L in f.levels:
+        L.loss = (S.LOSS_CAUCHY, scale)
+    cache = tmp_path / "tune.txt"
+    with open(cache, "w") as fh:
+        for L in f.levels:
+            fh.write(f"C{L.C}_d1_N{_floor_log2(L.N)}_M{_floor_log2(f.M)}_P{_floor_log2(L.H * L.W)}_v3 4 2 0 10\n")
+    c = Context(0, tune_cache=str(cache))
+    rng = np.random.default_rng(4)
+    poses = np.stack([oracle.compose(oracle.se3_exp(np.concatenate([rng.normal(0, 3, 3), rng.normal(0, 0.03, 3)])),
+                                     f.gt_pose) for _ in range(f.M)])
+    fm = mask_edges(copy.deepcopy(f), poses)
+    df = DeviceFrame(fm, dtype="bf16")
+    of = oracle.OracleFrame(fm)
+    say(f"fp32 cauchy scale={scale}")
+    for lvl in range(len(f.levels)):
+        _, _, cost, _ = c.linearize(df, lvl, torch.as_tensor(poses, device="cuda"))
+        cost = cost.cpu().numpy()
+        for m in range(f.M):
+            co = oracle.linearize(of, lvl, poses[m])[2]
+            assert abs(cost[m] - co) <= 1e-5 * abs(co), (lvl, m, cost[m], co)
+    c.close()
+
+
 @pytest.mark.parametrize("dtype,variant", [("f32", 3), ("f32", 7), ("bf16", 5), ("bf16", 8), ("bf16", 9),
                                            ("bf16", 10)])
 def test_shared_gathers_leave_sums_bitwise_unchanged(tmp_path, dtype, variant):
