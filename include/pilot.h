@@ -79,7 +79,9 @@ enum { PILOT_CONVERGED = 0, PILOT_MAX_ITERS = 1, PILOT_STALLED = 2, PILOT_DEGENE
 enum {
     PILOT_FLAG_NO_GRAPH = 1,  /* launch kernels directly instead of replaying a hipGraph */
     PILOT_FLAG_AUTOTUNE = 2,  /* time tile candidates on first use of a shape class     */
-    PILOT_FLAG_PROFILE = 4    /* time every pass launch with hipEvents (implies NO_GRAPH) */
+    PILOT_FLAG_PROFILE = 4,   /* time every pass launch with hipEvents (implies NO_GRAPH) */
+    PILOT_FLAG_KEEP_ORDER = 8,/* walk anchors in the caller's order (no spatial sort)     */
+    PILOT_FLAG_SORT_ANCHORS = 16 /* sort every level's anchors (2..16384 of them)          */
 };
 
 typedef struct pilot_ctx pilot_ctx;
@@ -98,7 +100,21 @@ typedef struct {
 /* One pyramid level (Eq. (1) at level l, scaled intrinsics K_l).  The kernels
  * address each level's arrays with 32-bit byte offsets: the map (H*W*C
  * elements), the descriptors (N*C elements) and the per-cell table the library
- * builds (80*H*W bytes) must each be under 4 GiB, else PILOT_EINVAL. */
+ * builds (80*H*W bytes) must each be under 4 GiB, else PILOT_EINVAL.
+ *
+ * Anchor order: the sums of Eq. (1) run over the anchors in an order the
+ * library picks, so the caller may list them in any order.  A level with
+ * 2 <= N <= 16384 anchors and N * M >= 2^23 anchor-hypothesis pairs per pass
+ * is walked in Morton order of the anchors' ground position (x, y on a
+ * 256 x 256 grid over their bounding box; anchors of one cell in the
+ * caller's order), from copies of x, y, z, ref and ref_w that the library
+ * makes in its workspace at the start of every solve (pilot_solve,
+ * pilot_solve_static, pilot_linearize) and at pilot_admit; the caller's
+ * arrays are only read.  Neighbouring anchors then project to neighbouring
+ * cells under one pose and share cache lines.  Results change only in the
+ * rounding of the sums.  Below 2^23 pairs the sort costs more than it saves
+ * and the caller's order is kept; PILOT_FLAG_SORT_ANCHORS sorts every level
+ * of 2..16384 anchors, PILOT_FLAG_KEEP_ORDER none (it wins over the other). */
 typedef struct {
     int32_t H, W, C;            /* C in {16, 32, 64, 128, 256}; H, W >= 2             */
     int32_t dtype;              /* PILOT_F32 or PILOT_BF16, for feat and ref         */

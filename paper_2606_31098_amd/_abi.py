@@ -12,7 +12,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 F32, BF16 = 0, 1
 LOSS_CAUCHY, LOSS_HUBER, LOSS_L2 = 0, 1, 2
 CONVERGED, MAX_ITERS, STALLED, DEGENERATE, PRUNED = 0, 1, 2, 3, 4
-FLAG_NO_GRAPH, FLAG_AUTOTUNE, FLAG_PROFILE = 1, 2, 4
+FLAG_NO_GRAPH, FLAG_AUTOTUNE, FLAG_PROFILE, FLAG_KEEP_ORDER, FLAG_SORT_ANCHORS = 1, 2, 4, 8, 16
 
 ERROR_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE",
                EAGAIN: "EAGAIN", EUNSUPPORTED: "EUNSUPPORTED"}

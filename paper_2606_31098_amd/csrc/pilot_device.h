@@ -31,7 +31,17 @@ struct LevelDev {
     // coefficients of cell (x0, y0) at index y0 W + x0, 10 doubles per cell
     // (variants 3 to 8) or 12 floats (variants 9 and 10: 10 entries, 2 pads)
     const double *gram;
+    // anchors in spatial order: when perm is set, x, y, z, ref and ref_w point
+    // at the library's copies in Morton order of the anchors' ground position
+    // (perm[j] = caller index of anchor j) and in_* at the caller's arrays
+    const float *in_x, *in_y, *in_z, *in_w;
+    const void *in_ref;
+    int *perm;
 };
+
+// Anchor sets of up to this many anchors are sorted into spatial order
+// (larger ones are taken in the caller's order).
+constexpr int kSortMaxN = 16384;
 
 // One frame (solve) or one serving slot.
 struct FrameDev {

@@ -65,6 +65,12 @@ hipError_t launch_pack(const FrameDev *frames, int n_frames, int max_M, const in
                        const HypState *hs, const PoseEval *pose, HypState *phs, PoseEval *ppose, int *pcount,
                        int *pclear0, int *pclear1, hipStream_t s);
 
+// Spatial order of the anchors of every level with a permutation buffer
+// (LevelDev::perm non-NULL and N <= kSortMaxN): the permutation, then the
+// copies x, y, z, ref, ref_w of the caller's in_* arrays in that order.
+// Grid: max_levels x n_frames sort blocks, then the copy; max_N bounds N.
+hipError_t launch_anchor_sort(const FrameDev *frames, int n_frames, int max_levels, int max_N, hipStream_t s);
+
 // Write results of every frame whose hypotheses have all finished and that
 // has not been finalised yet (done_flag == 0), including the argmin.
 hipError_t launch_finalize(const FrameDev *frames, int n_frames, const HypState *hs,

@@ -753,4 +753,256 @@ hipError_t launch_pack(const FrameDev *frames, int n_frames, int max_M, const in
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Anchors in spatial order.  The pass kernels walk a level's anchors in array
+// order, P at a time per work item, so the locality of their gathers (taps of
+// neighbouring anchors under one pose fall in neighbouring cells, sharing
+// cache lines in L1 and L2) depends on how the caller listed the anchors.
+// The library therefore sorts each level's anchors by the Morton code of
+// their ground position (x, y quantised to 64 x 64 cells over the level's
+// bounding box) before the first pass and walks its own copies.  The sums
+// over anchors change only in their rounding order; the order is a function
+// of the anchor set alone (ties of one cell keep the caller's order).
+
+namespace {
+constexpr int kSortThreads = 1024;
+typedef uint32_t row16 __attribute__((ext_vector_type(4)));   // 16 bytes of a reference row
+
+// The thread index, opaque to the optimiser: element indices derived from it
+// are recomputed in each loop instead of being kept live (and spilled)
+// across the whole kernel.
+__device__ __forceinline__ int fresh_tid()
+{
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+__device__ __forceinline__ uint32_t spread_bits8(uint32_t v)
+{
+    v &= 0xffu;
+    v = (v | (v << 4)) & 0x0f0fu;
+    v = (v | (v << 2)) & 0x3333u;
+    v = (v | (v << 1)) & 0x5555u;
+    return v;
+}
+}  // namespace
+
+// One block per (level, frame): keys (Morton code << 16 | caller index) in
+// LDS, sorted on the 12-bit code by a stable least-significant-digit radix
+// sort (three passes of 4 bits), so anchors of one cell keep the caller's
+// order; perm[j] = caller index of the j-th anchor in spatial order.
+//
+// A pass over element i = r kSortThreads + tid (r < kSortPer): the 32
+// elements of one half-wave and round form group i / 32 (groups in element
+// order).  Each element learns from four ballots the lanes of its group with
+// the same digit (its rank among them, and the leader of them writes their
+// count to cnt[group][digit]); the waves then scan each digit's counts over
+// the groups, and a second sweep moves every element to the start of its
+// digit + the count of its digit in the groups before its own + its rank.
+// The passes alternate between the keys in LDS and the permutation buffer
+// (global memory, N words), so no pass holds its keys in registers.
+template <int kSortPer>   // anchors per thread: N <= kSortPer kSortThreads
+__global__ __launch_bounds__(kSortThreads) void sort_anchors_kernel(const FrameDev *frames)
+{
+    constexpr int kCap = kSortPer * kSortThreads;
+    __shared__ uint32_t s_key[kCap];
+    constexpr int kGroups = kCap / 32, kStride = kGroups + 2;   // padded rows: no bank conflicts
+    __shared__ unsigned short s_cnt[16][kStride];   // [digit][group]
+    __shared__ uint32_t s_dtot[16], s_dstart[16];
+    __shared__ float s_bb[kSortThreads / 64][4];
+    const FrameDev &f = frames[blockIdx.y];
+    const int l = blockIdx.x;
+    if (l >= f.n_levels) return;
+    const LevelDev &L = f.lv[l];
+    int *perm = L.perm;
+    const int N = L.N;
+    if (!perm || N <= 0 || N > kCap) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    typedef const __attribute__((address_space(1))) float gfloat;
+    gfloat *xs = (gfloat *)L.in_x, *ys = (gfloat *)L.in_y;
+    // the thread's anchors tid + r kSortThreads, loaded in one round trip
+    // (clamped indices: no branch between the loads), and the bounding box of
+    // their ground positions (as -min, max, so every step is a max; repeats
+    // of anchor N - 1 change no extreme)
+    float xv[kSortPer], yv[kSortPer];
+    float b[4] = {-3.4e38f, -3.4e38f, -3.4e38f, -3.4e38f};
+    {
+        const int tl = fresh_tid();
+#pragma unroll
+        for (int r = 0; r < kSortPer; ++r) {
+            const int i = min(tl + r * kSortThreads, N - 1);
+            xv[r] = xs[i];
+            yv[r] = ys[i];
+        }
+#pragma unroll
+        for (int r = 0; r < kSortPer; ++r) {
+            b[0] = fmaxf(b[0], -xv[r]);
+            b[1] = fmaxf(b[1], xv[r]);
+            b[2] = fmaxf(b[2], -yv[r]);
+            b[3] = fmaxf(b[3], yv[r]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int sft = 1; sft < 64; sft <<= 1) b[k] = fmaxf(b[k], __shfl_xor(b[k], sft, 64));
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s_bb[wave][k] = b[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        b[k] = s_bb[0][k];
+        for (int w = 1; w < kSortThreads / 64; ++w) b[k] = fmaxf(b[k], s_bb[w][k]);
+    }
+    const float x0 = -b[0], y0 = -b[2];
+    const float sx = b[1] + b[0] > 0.0f ? 256.0f / (b[1] + b[0]) : 0.0f;
+    const float sy = b[3] + b[2] > 0.0f ? 256.0f / (b[3] + b[2]) : 0.0f;
+    const int tk = fresh_tid();
+#pragma unroll
+    for (int r = 0; r < kSortPer; ++r) {
+        const int i = tk + r * kSortThreads;
+        if (i < N) {
+            const uint32_t qx = (uint32_t)fminf(fmaxf((xv[r] - x0) * sx, 0.0f), 255.0f);
+            const uint32_t qy = (uint32_t)fminf(fmaxf((yv[r] - y0) * sy, 0.0f), 255.0f);
+            s_key[i] = ((spread_bits8(qx) | (spread_bits8(qy) << 1)) << 16) | (uint32_t)i;
+        }
+    }
+    const int ngroups = (N + 31) >> 5;
+    const uint32_t below = (1u << (lane & 31)) - 1u;
+    const bool upper = lane >= 32;
+    typedef __attribute__((address_space(1))) uint32_t guint;
+    guint *gk = (guint *)perm;     // the other buffer of the passes (N words)
+    // the keys of the thread's elements in the pass's source, loaded in one
+    // round trip (indices beyond N read a valid slot and go unused)
+    auto load_keys = [&](bool from_lds, uint32_t (&kv)[kSortPer]) {
+        const int t = fresh_tid();
+#pragma unroll
+        for (int r = 0; r < kSortPer; ++r) {
+            const int i = t + r * kSortThreads;
+            kv[r] = from_lds ? s_key[min(i, kCap - 1)] : gk[min(i, N - 1)];
+        }
+    };
+    // the lanes of element i's group (its half of the wave) with the same digit d
+    auto peers_of = [&](int i, uint32_t d) {
+        const unsigned long long v = __ballot(i < N);
+        uint32_t peers = upper ? (uint32_t)(v >> 32) : (uint32_t)v;
+#pragma unroll
+        for (int bit = 0; bit < 4; ++bit) {
+            const unsigned long long m = __ballot((d >> bit) & 1u);
+            const uint32_t mh = upper ? (uint32_t)(m >> 32) : (uint32_t)m;
+            peers &= ((d >> bit) & 1u) ? mh : ~mh;
+        }
+        return peers;
+    };
+#pragma unroll 1
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 16 + 4 * pass;
+        const bool from_lds = (pass & 1) == 0;    // LDS -> global, then global -> LDS
+        for (int e = tid; e < 16 * kStride; e += kSortThreads) (&s_cnt[0][0])[e] = 0;
+        __syncthreads();
+        {
+            uint32_t kv[kSortPer];
+            load_keys(from_lds, kv);
+            const int ta = fresh_tid();
+#pragma unroll
+            for (int r = 0; r < kSortPer; ++r) {
+                const int i = ta + r * kSortThreads;
+                const uint32_t d = (kv[r] >> shift) & 15u;
+                const uint32_t peers = peers_of(i, d);
+                if (i < N && (peers & below) == 0u) s_cnt[d][i >> 5] = (unsigned short)__popc(peers);
+            }
+        }
+        __syncthreads();
+        {
+            // wave d: exclusive scan of digit d's counts over the groups, a row
+            // of 64 groups at a time
+            static_assert(kSortThreads / 64 == 16, "one wave per digit");
+            const int d = wave;
+            uint32_t carry = 0;
+            for (int g0 = 0; g0 < ngroups; g0 += 64) {
+                const int g = g0 + lane;
+                const uint32_t c = g < ngroups ? s_cnt[d][g] : 0u;
+                uint32_t incl = c;
+#pragma unroll
+                for (int sft = 1; sft < 64; sft <<= 1) {
+                    const uint32_t o = __shfl_up(incl, sft, 64);
+                    if (lane >= sft) incl += o;
+                }
+                if (g < ngroups) s_cnt[d][g] = (unsigned short)(carry + incl - c);
+                carry += __shfl(incl, 63, 64);
+            }
+            if (lane == 0) s_dtot[d] = carry;
+        }
+        __syncthreads();
+        if (tid < 16) {
+            uint32_t acc = 0;
+            for (int d = 0; d < tid; ++d) acc += s_dtot[d];
+            s_dstart[tid] = acc;
+        }
+        __syncthreads();
+        {
+            uint32_t kv[kSortPer];
+            load_keys(from_lds, kv);
+            const int tb = fresh_tid();
+#pragma unroll
+            for (int r = 0; r < kSortPer; ++r) {
+                const int i = tb + r * kSortThreads;
+                const uint32_t d = (kv[r] >> shift) & 15u;
+                const uint32_t peers = peers_of(i, d);
+                if (i < N) {
+                    const uint32_t dst = s_dstart[d] + s_cnt[d][i >> 5] + (uint32_t)__popc(peers & below);
+                    if (from_lds) gk[dst] = kv[r];
+                    else s_key[dst] = kv[r];
+                }
+            }
+        }
+        __syncthreads();                          // also orders the block's global stores before the next pass
+    }
+    for (int i = tid; i < N; i += kSortThreads) perm[i] = (int)(s_key[i] & 0xffffu);
+}
+
+// Copies of the anchors in perm order: 64 anchors per block, the reference
+// rows moved 16 bytes per thread and load.
+__global__ __launch_bounds__(256) void gather_anchors_kernel(const FrameDev *frames)
+{
+    const FrameDev &f = frames[blockIdx.z];
+    const int l = blockIdx.y;
+    if (l >= f.n_levels) return;
+    const LevelDev &L = f.lv[l];
+    const int *perm = L.perm;
+    const int N = L.N;
+    const int a0 = blockIdx.x * 64;
+    if (!perm || N > kSortMaxN || a0 >= N) return;
+    const int na = min(64, N - a0);
+    const int cpr = L.C * (L.dtype == 1 ? 2 : 4) / 16;    // 16-byte chunks per reference row
+    const row16 *src = (const row16 *)L.in_ref;
+    row16 *dst = (row16 *)const_cast<void *>(L.ref);
+    for (int t = threadIdx.x; t < na * cpr; t += 256) {
+        const int a = t / cpr, c = t - a * cpr;
+        dst[(size_t)(a0 + a) * cpr + c] = src[(size_t)min(max(perm[a0 + a], 0), N - 1) * cpr + c];
+    }
+    if ((int)threadIdx.x < na) {
+        const int a = a0 + threadIdx.x, i = min(max(perm[a], 0), N - 1);
+        const_cast<float *>(L.x)[a] = L.in_x[i];
+        const_cast<float *>(L.y)[a] = L.in_y[i];
+        const_cast<float *>(L.z)[a] = L.in_z[i];
+        if (L.in_w) const_cast<float *>(L.ref_w)[a] = L.in_w[i];
+    }
+}
+
+hipError_t launch_anchor_sort(const FrameDev *frames, int n_frames, int max_levels, int max_N, hipStream_t s)
+{
+    if (n_frames <= 0 || max_levels <= 0 || max_N <= 0) return hipSuccess;
+    if (max_levels > kMaxLevels || max_N > kSortMaxN) return hipErrorInvalidValue;
+    const dim3 sg(max_levels, n_frames);
+    static_assert(kSortMaxN == 16 * kSortThreads, "sort instantiations");
+    if (max_N <= 4 * kSortThreads) hipLaunchKernelGGL(sort_anchors_kernel<4>, sg, dim3(kSortThreads), 0, s, frames);
+    else if (max_N <= 8 * kSortThreads) hipLaunchKernelGGL(sort_anchors_kernel<8>, sg, dim3(kSortThreads), 0, s, frames);
+    else hipLaunchKernelGGL(sort_anchors_kernel<16>, sg, dim3(kSortThreads), 0, s, frames);
+    hipLaunchKernelGGL(gather_anchors_kernel, dim3((max_N + 63) / 64, max_levels, n_frames), dim3(256), 0, s, frames);
+    return hipGetLastError();
+}
+
 }  // namespace pilot

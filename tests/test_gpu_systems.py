@@ -1,4 +1,5 @@
 """Batching, graph replay, serving and ABI error behaviour of libpilot on the GPU."""
+import copy
 import ctypes as C
 import math
 
@@ -8,7 +9,7 @@ import torch
 
 import oracle
 from synth import frames as S
-from tests.gpu_common import POSE_TOL_DEG, POSE_TOL_M, compare_solutions, mask_edges, rel_frobenius, say, unpack_h21
+from tests.gpu_common import BF16_TOL_DEG, BF16_TOL_M, POSE_TOL_DEG, POSE_TOL_M, compare_solutions, mask_edges, rel_frobenius, say, unpack_h21
 
 pytestmark = pytest.mark.gpu
 
@@ -177,6 +178,105 @@ def test_serving_admission_by_budget_and_slots(alone):
     assert ctx2.admit(dfs[2], DeviceResult(dfs[2].M)) is not None
     assert ctx2.admit(dfs[3], DeviceResult(dfs[3].M)) is None
     assert "slots" in ctx2.last_error()
+
+
+def permuted(frame, order):
+    """The frame with every level's anchors listed in `order`."""
+    f = copy.deepcopy(frame)
+    for L in f.levels:
+        L.x, L.y, L.z, L.ref = (np.ascontiguousarray(a[order]) for a in (L.x, L.y, L.z, L.ref))
+        if L.ref_w is not None:
+            L.ref_w = np.ascontiguousarray(L.ref_w[order])
+    return f
+
+
+def serve_one(ctx, d):
+    from paper_2606_31098_amd.pilot import DeviceResult
+    res = DeviceResult(d.M)
+    s = ctx.admit(d, res)
+    assert s is not None, ctx.last_error()
+    n = 0
+    while not ctx.poll(s):
+        ctx.step()
+        ctx.sync()
+        n += 1
+        assert n < 400, "serving did not drain"
+    torch.cuda.synchronize()
+    return as_np(res)
+
+
+def test_anchor_order_does_not_change_results(alone):
+    """With the anchors sorted into spatial order (PILOT_FLAG_SORT_ANCHORS),
+    the frame with its anchors shuffled (one anchor per DSM sample: no two
+    share a sort cell) solves to bitwise the same results as the frame in its
+    generator order, by pilot_solve, pilot_solve_static and serving, and
+    linearizes to the same normal equations.  In the caller's order
+    (PILOT_FLAG_KEEP_ORDER) both listings agree with the sorted solve within
+    the FP32 tolerance."""
+    from paper_2606_31098_amd import _abi as A
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    fr, dfs, ref = alone
+    f = fr[0]
+    order = np.random.default_rng(3).permutation(f.levels[0].N)
+    dg = DeviceFrame(permuted(f, order))
+    say("shuffled anchors, sorted: solve, static solve, serving")
+    ctx = Context(0, flags=A.FLAG_SORT_ANCHORS)
+    r0 = as_np(ctx.solve([dfs[0]])[0])
+    a = as_np(ctx.solve([dg])[0])
+    b = as_np(ctx.solve_static([dg])[0])
+    c = serve_one(Context(0, max_slots=2, flags=A.FLAG_SORT_ANCHORS), dg)
+    poses = torch.as_tensor(f.poses, device="cuda")
+    lin0 = ctx.linearize(dfs[0], 1, poses)
+    lin1 = ctx.linearize(dg, 1, poses)
+    keep = Context(0, flags=A.FLAG_KEEP_ORDER)
+    k0 = as_np(keep.solve([dfs[0]])[0])
+    k1 = as_np(keep.solve([dg])[0])
+    torch.cuda.synchronize()
+    assert same(a, r0) and same(b, r0) and same(c, r0)
+    for x, y in zip(lin0, lin1):
+        assert torch.equal(x, y)
+    assert same(k0, ref[0])               # small problems keep the caller's order by default
+    for k, name in ((k0, "caller order"), (k1, "shuffled, caller order")):
+        rows, fails = compare_solutions(f, k, r0, POSE_TOL_M, POSE_TOL_DEG, name)
+        assert not fails, fails
+
+
+def test_default_sorts_only_large_levels():
+    """By default a level is sorted when it has at least 2^23 anchor x
+    hypothesis pairs per pass: a frame of 8192 anchors and 1024 hypotheses
+    solves as with PILOT_FLAG_SORT_ANCHORS, bitwise, and differs from its
+    caller-order solve only by the rounding of the sums (after three LM
+    iterations per level the hypotheses are still moving, so that rounding
+    shows at the 1e-4 m / 1e-4 degree level: compared at the BF16 tolerance)."""
+    from paper_2606_31098_amd import _abi as A
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    f = small(33, N=8192, M=1024, levels=((30, 40, 16), (60, 80, 32)), iters=(3, 3))
+    say("8192 anchors x 1024 hypotheses: default vs sorted vs caller order")
+    d = DeviceFrame(f)
+    a = as_np(Context(0).solve([d])[0])
+    b = as_np(Context(0, flags=A.FLAG_SORT_ANCHORS).solve([d])[0])
+    k = as_np(Context(0, flags=A.FLAG_KEEP_ORDER).solve([d])[0])
+    torch.cuda.synchronize()
+    assert same(a, b)
+    assert not same(a, k)                 # the sorted sums were rounded in another order
+    rows, fails = compare_solutions(f, k, a, BF16_TOL_M, BF16_TOL_DEG, "caller order")
+    assert not fails, fails
+
+
+def test_levels_above_the_sort_limit_keep_the_caller_order():
+    """Levels of more than 16384 anchors are walked in the caller's order even
+    under PILOT_FLAG_SORT_ANCHORS: that context and one with
+    PILOT_FLAG_KEEP_ORDER give bitwise the same results for such a frame."""
+    from paper_2606_31098_amd import _abi as A
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    f = S.make_frame(2, 0, N=17000, M=3, level_shapes=((30, 40, 16), (60, 80, 32)), iters=(3, 3),
+                     dsm_side=256, seed=41)
+    say("levels of 17000 anchors: sorted vs caller order")
+    d = DeviceFrame(f)
+    a = as_np(Context(0, flags=A.FLAG_SORT_ANCHORS).solve([d])[0])
+    b = as_np(Context(0, flags=A.FLAG_KEEP_ORDER).solve([d])[0])
+    torch.cuda.synchronize()
+    assert same(a, b)
 
 
 def test_device_hypotheses_from_prior():
