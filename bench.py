@@ -236,7 +236,10 @@ def cpu_leg(args, frames):
 def vs_oracle(frame, gpu, orc):
     """Pose difference of the GPU result from the oracle's on the hypotheses
     the oracle solved: over hypotheses converged (within 1 m / 1 deg of the
-    truth) in both, and how many verdicts agree."""
+    truth) in both that ran every level, and how many verdicts agree.
+    Hypotheses pruned in both (top-K after the pruning level) stop after that
+    level's few iterations, mid-descent, so their poses are reported apart
+    (`pruned_*`): the selection never reads them."""
     import numpy as np
 
     from synth import frames as S
@@ -244,15 +247,22 @@ def vs_oracle(frame, gpu, orc):
     tg, rg = S.pose_errors(gpu["poses"][idx], frame.gt_pose)
     to, ro = S.pose_errors(orc["poses"], frame.gt_pose)
     vg, vo = (tg <= 1.0) & (rg <= 1.0), (to <= 1.0) & (ro <= 1.0)
-    both = vg & vo
+    pruned = (np.asarray(gpu["status"])[idx] == 4) & (np.asarray(orc["status"]) == 4)
+    both = vg & vo & ~pruned
+    pb = vg & vo & pruned
     dt = np.array([S.pose_errors(gpu["poses"][i], orc["poses"][k])[0][0] for k, i in enumerate(idx)])
     dr = np.array([S.pose_errors(gpu["poses"][i], orc["poses"][k])[1][0] for k, i in enumerate(idx)])
-    return {"hypotheses": int(len(idx)), "verdicts_agree": int(np.sum(vg == vo)),
-            "converged_in_both": int(both.sum()),
-            "max_m": float(dt[both].max()) if both.any() else None,
-            "median_m": float(np.median(dt[both])) if both.any() else None,
-            "max_deg": float(dr[both].max()) if both.any() else None,
-            "median_deg": float(np.median(dr[both])) if both.any() else None}
+    out = {"hypotheses": int(len(idx)), "verdicts_agree": int(np.sum(vg == vo)),
+           "converged_in_both": int(both.sum()),
+           "max_m": float(dt[both].max()) if both.any() else None,
+           "median_m": float(np.median(dt[both])) if both.any() else None,
+           "max_deg": float(dr[both].max()) if both.any() else None,
+           "median_deg": float(np.median(dr[both])) if both.any() else None}
+    if pruned.any():
+        out.update({"pruned_in_both": int(pruned.sum()), "pruned_near_truth": int(pb.sum()),
+                    "pruned_max_m": float(dt[pb].max()) if pb.any() else None,
+                    "pruned_max_deg": float(dr[pb].max()) if pb.any() else None})
+    return out
 
 
 def line(args, value, steps, warmup, ms, dtype, workload, extra):
