@@ -238,7 +238,8 @@ int pilot_solve(pilot_ctx *ctx, const pilot_frame *frames, int n_frames,
 /* pilot_solve for callers that cannot allocate device memory (code under
  * hipGraph capture, tight serving loops, hosts that forbid hipMalloc): the
  * same schedule and kernels, with every piece of workspace (descriptors,
- * Gram tables, LM states, partial sums, pass flags) carved from one fixed
+ * Gram tables, spatially ordered anchor copies, LM states, partial sums,
+ * pass flags) carved from one fixed
  * device array of PILOT_STATIC_SCRATCH_BYTES per GPU that the library holds
  * from the first pilot_create on that GPU until the process ends.  Calls no
  * hipMalloc, hipFree, pinned-memory allocation or graph instantiation: the
