@@ -55,7 +55,13 @@ struct LaunchGroup {
     int tile_off = 0, n_tiles = 0;
     int passes = 0;
     int stat_class = 0;
+    size_t partial_off = 0;   // its partial records in the partials buffer (floats)
 };
+
+// Side streams of a context: the launch groups of one pass run concurrently
+// on the context's stream and up to kSideStreams more, forked and joined
+// through events around every pass (captured into the solve's graph).
+constexpr int kSideStreams = 3;
 
 struct Plan {
     std::vector<FrameDev> frames;
@@ -111,6 +117,8 @@ struct pilot_ctx {
     int flags = 0;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
+    hipStream_t side[kSideStreams] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[kSideStreams] = {};
     size_t budget = 0;
     std::string tune_cache;
     int max_slots = 64;
@@ -593,6 +601,7 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
         // each frame's tiles depend on its own shape only, so its sums (and
         // results) are the same alone or batched with any other frames
         std::map<std::array<int, 6>, std::vector<int>> by_class;
+        size_t level_partials = 0;
         for (int i = 0; i < n; ++i)
             if (l < frames[i].n_levels) {
                 const pilot_level &L = frames[i].level[l];
@@ -637,7 +646,10 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
                     key << "|g" << i << "." << l << ":" << Li.H << "x" << Li.W << "x" << Li.C << "d" << Li.dtype
                         << "f" << fmt;
                 }
-            plan.partial_floats = std::max(plan.partial_floats, (size_t)g.n_items * g.tc.G * kNV);
+            // the groups of a level run concurrently: disjoint partial records
+            g.partial_off = level_partials;
+            level_partials += (size_t)g.n_items * g.tc.G * kNV;
+            plan.partial_floats = std::max(plan.partial_floats, level_partials);
             plan.groups.push_back(g);
             key << "|l" << l << "c" << g.C << "d" << g.dtype << "G" << g.tc.G << "p" << g.tc.PPG << "g" << g.tc.grid
                 << "v" << g.tc.variant << "k" << g.tc.pack << "i" << g.n_items << "t" << g.n_tiles << "s" << g.passes;
@@ -780,7 +792,7 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Ws &
     a.level = g.level;
     a.pose = ws.pose;
     a.hlev = ws.hlev;
-    a.partials = ws.partials;
+    a.partials = ws.partials + g.partial_off;
     a.run_flag = run_flag;
     if (packed) {
         a.ppose = ws.ppose + (size_t)b0 * ws.hyps;
@@ -810,7 +822,7 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Ws &
     e.level = g.level;
     e.G = g.tc.G;
     e.mode = mode;
-    e.partials = ws.partials;
+    e.partials = ws.partials + g.partial_off;
     e.pose = ws.pose;
     e.hlev = ws.hlev;
     e.hs = ws.hs;
@@ -878,14 +890,35 @@ int enqueue_schedule(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const 
         bool prunes = false;
         for (const FrameDev &f : plan.frames) prunes = prunes || (f.keep_top > 0 && f.prune_level == l);
         for (int k = 0; k < maxp; ++k) {
+            // the pass's launch groups (disjoint frames, disjoint partial
+            // records) run concurrently: the largest first, each on the least
+            // loaded of the context's stream and its side streams
+            std::vector<const LaunchGroup *> gs;
             for (const LaunchGroup &g : plan.groups)
-                if (g.level == l && k < g.passes) {
-                    // pass k of level l runs only if pass k - 1 left a hypothesis at level l
-                    int *flags = ws.passflag + (size_t)l * plan.flag_stride;
-                    int rc = enqueue_pass(ctx, plan, dp, wp, g, MODE_LM, s, timed, flags + k, flags + k + 1, false,
-                                          pack, k);
-                    if (rc) return rc;
-                }
+                if (g.level == l && k < g.passes) gs.push_back(&g);
+            std::stable_sort(gs.begin(), gs.end(),
+                             [](const LaunchGroup *a, const LaunchGroup *b) { return a->n_items > b->n_items; });
+            const int nside = std::min<int>(kSideStreams, (int)gs.size() - 1);
+            if (nside > 0) {
+                HIPCHK(ctx, hipEventRecord(ctx->fork_ev, s));
+                for (int i = 0; i < nside; ++i) HIPCHK(ctx, hipStreamWaitEvent(ctx->side[i], ctx->fork_ev, 0));
+            }
+            long load[1 + kSideStreams] = {0};
+            for (const LaunchGroup *g : gs) {
+                int q = 0;
+                for (int i = 1; i <= nside; ++i)
+                    if (load[i] < load[q]) q = i;
+                load[q] += g->n_items;
+                // pass k of level l runs only if pass k - 1 left a hypothesis at level l
+                int *flags = ws.passflag + (size_t)l * plan.flag_stride;
+                int rc = enqueue_pass(ctx, plan, dp, wp, *g, MODE_LM, q ? ctx->side[q - 1] : s, timed, flags + k,
+                                      flags + k + 1, false, pack, k);
+                if (rc) return rc;
+            }
+            for (int i = 0; i < nside; ++i) {
+                HIPCHK(ctx, hipEventRecord(ctx->join_ev[i], ctx->side[i]));
+                HIPCHK(ctx, hipStreamWaitEvent(s, ctx->join_ev[i], 0));
+            }
         }
         if (prunes) HIPCHK(ctx, launch_prune(dp.frames, nf, ws.hs, ws.pose, ws.hlev, s));
         if (pack && l + 1 < plan.max_levels) HIPCHK(ctx, pack_level(l + 1));
@@ -976,6 +1009,9 @@ int pilot_create(pilot_ctx **out, const pilot_config *cfg)
     ctx->max_slots = cfg->max_slots ? cfg->max_slots : 64;
     ctx->ncu = prop.multiProcessorCount;
     e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+    for (int i = 0; i < kSideStreams && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming);
+    for (int i = 0; i < kSideStreams && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ctx->join_ev[i], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->stage[0].ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->stage[1].ev, hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -1022,6 +1058,11 @@ void pilot_destroy(pilot_ctx *ctx)
         if (sl.gram.p) hipFree(sl.gram.p);
         if (sl.anch.p) hipFree(sl.anch.p);
     }
+    for (int i = 0; i < kSideStreams; ++i) {
+        if (ctx->side[i]) hipStreamSynchronize(ctx->side[i]), hipStreamDestroy(ctx->side[i]);
+        if (ctx->join_ev[i]) hipEventDestroy(ctx->join_ev[i]);
+    }
+    if (ctx->fork_ev) hipEventDestroy(ctx->fork_ev);
     if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     delete ctx;
 }
