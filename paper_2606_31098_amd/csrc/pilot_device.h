@@ -26,7 +26,12 @@ struct LevelDev {
     int H, W, C, N;
     int iters, loss_kind;
     double loss_b;
-    int dtype, pad;
+    int dtype;
+    // the level's tile for this frame: anchors per lane group (a work item
+    // covers kBlock / G * ppg anchors) and the packed-tile threshold of
+    // use_packed (INT_MAX: never packed); frames with different values share
+    // a launch when their kernel instantiation is the same
+    int ppg, pack_min, pad;
     // pass kernel variants 3 to 10: per-cell Gram matrices of the bilinear
     // coefficients of cell (x0, y0) at index y0 W + x0, 10 doubles per cell
     // (variants 3 to 8) or 12 floats (variants 9 and 10: 10 entries, 2 pads)
@@ -141,7 +146,6 @@ struct PassArgs {
     const int *pcount;
     int *pcount_clear;
     int n_frames;
-    int pack_min;                // see use_packed
 };
 
 struct EpilogueArgs {
@@ -171,7 +175,6 @@ struct EpilogueArgs {
     HypState *phs_next;
     PoseEval *ppose_next;
     int *pcount_next;
-    int pack_min;                // see use_packed
 };
 
 // Packed or contiguous hypothesis tiles for one frame in one pass: packed when

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kEpiBlock) void epilogue_kernel(EpilogueArgs e)
     // pass's lists.
     const bool lists = e.phs != nullptr;
     const int cnt = lists ? e.pcount[ti.frame] : 0;
-    const bool packed = lists && use_packed(cnt, f->M, G, ti.n_ptiles, e.pack_min);
+    const bool packed = lists && use_packed(cnt, f->M, G, ti.n_ptiles, f->lv[e.level].pack_min);
     const int nh = packed ? min(ti.nh, cnt - ti.htile * G) : ti.nh;
     if (packed && nh <= 0) return;               // past the hypotheses still at the level
     const HypState *hs_in = (packed ? e.phs : e.hs) + hb;

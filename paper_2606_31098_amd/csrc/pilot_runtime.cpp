@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <array>
 #include <cmath>
 #include <cstdarg>
@@ -571,6 +572,15 @@ void place_anchor_copy(LevelDev &o, char *p)
     o.ref = p + off;
 }
 
+// The packed-tile threshold of a tile (use_packed): mode 0 never packs, mode
+// 1 packs when the tiles that may be active hold more work items than four
+// per CU, mode 2 always.
+int pack_min_of(const pilot_ctx *ctx, const TileConfig &tc)
+{
+    if (!uses_gram(tc) || tc.pack == 0) return INT_MAX;
+    return tc.pack == 2 ? 0 : 4 * ctx->ncu;
+}
+
 // Build the schedule: per level, frames grouped by (C, dtype), each group a
 // list of (hypothesis tile x anchor tile) work items.
 void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pilot_result *results,
@@ -598,38 +608,51 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
     key << "n" << n << "_h" << base << "_m" << plan.max_M << "_a" << plan.anchor_max_N << "." << plan.anchor_jobs.size();
     for (int l = 0; l < plan.max_levels; ++l) {
         if (only_level >= 0 && l != only_level) continue;
-        // each frame's tiles depend on its own shape only, so its sums (and
-        // results) are the same alone or batched with any other frames
-        std::map<std::array<int, 6>, std::vector<int>> by_class;
+        // each frame's tile depends on its own shape only, so its sums (and
+        // results) are the same alone or batched with any other frames;
+        // frames whose tiles share a kernel instantiation (C, dtype, G,
+        // variant) share a launch, each walked with its own anchors per lane
+        // group and packing rule (LevelDev::ppg, pack_min)
+        std::map<std::array<int, 4>, std::vector<int>> by_class;
+        std::vector<TileConfig> tci(n);
         size_t level_partials = 0;
         for (int i = 0; i < n; ++i)
             if (l < frames[i].n_levels) {
                 const pilot_level &L = frames[i].level[l];
-                const TileConfig tc = choose_tile(ctx, L.C, L.dtype, L.N, frames[i].M, (long)L.H * L.W);
-                by_class[{L.C, L.dtype, tc.G, tc.PPG, tc.variant, tc.pack}].push_back(i);
+                tci[i] = choose_tile(ctx, L.C, L.dtype, L.N, frames[i].M, (long)L.H * L.W);
+                LevelDev &o = plan.frames[i].lv[l];
+                o.ppg = tci[i].PPG;
+                o.pack_min = pack_min_of(ctx, tci[i]);
+                by_class[{L.C, L.dtype, tci[i].G, tci[i].variant}].push_back(i);
             }
         for (auto &kv : by_class) {
             LaunchGroup g{};
             g.level = l;
             g.C = kv.first[0];
             g.dtype = kv.first[1];
-            int iters = 0;
-            for (int i : kv.second) iters = std::max(iters, frames[i].level[l].iters);
-            const pilot_level &L0 = frames[kv.second[0]].level[l];
-            g.tc = choose_tile(ctx, g.C, g.dtype, L0.N, frames[kv.second[0]].M, (long)L0.H * L0.W);
+            int iters = 0, pack = 0;
+            for (int i : kv.second) {
+                iters = std::max(iters, frames[i].level[l].iters);
+                pack = std::max(pack, tci[i].pack);
+            }
             g.item_off = (int)plan.items.size();
             g.tile_off = (int)plan.tiles.size();
+            int most = -1, most_items = -1;    // the launch takes the grid rule of the frame with most items
             for (int i : kv.second) {
-                const int nht = (frames[i].M + g.tc.G - 1) / g.tc.G;
-                const int npt = n_ptiles_of(g.tc, frames[i].level[l].N);
+                const TileConfig &t = tci[i];
+                const int nht = (frames[i].M + t.G - 1) / t.G;
+                const int npt = n_ptiles_of(t, frames[i].level[l].N);
+                if (nht * npt > most_items) most = i, most_items = nht * npt;
                 for (int ht = 0; ht < nht; ++ht) {
-                    const int h0 = ht * g.tc.G, nh = std::min(g.tc.G, frames[i].M - h0);
+                    const int h0 = ht * t.G, nh = std::min(t.G, frames[i].M - h0);
                     plan.tiles.push_back(
                         TileItem{i, ht, (int)plan.items.size() - g.item_off, npt, plan.frames[i].hyp_base + h0, nh});
                     for (int pt = 0; pt < npt; ++pt)
                         plan.items.push_back(WorkItem{i, plan.frames[i].hyp_base + h0, pt, nh});
                 }
             }
+            g.tc = tci[most];
+            g.tc.pack = pack;                   // packed lists when any frame of the launch packs
             g.n_items = (int)plan.items.size() - g.item_off;
             g.n_tiles = (int)plan.tiles.size() - g.tile_off;
             g.passes = (only_level >= 0) ? 1 : 1 + iters;
@@ -651,8 +674,8 @@ void build_plan(const pilot_ctx *ctx, const pilot_frame *frames, int n, const pi
             level_partials += (size_t)g.n_items * g.tc.G * kNV;
             plan.partial_floats = std::max(plan.partial_floats, level_partials);
             plan.groups.push_back(g);
-            key << "|l" << l << "c" << g.C << "d" << g.dtype << "G" << g.tc.G << "p" << g.tc.PPG << "g" << g.tc.grid
-                << "v" << g.tc.variant << "k" << g.tc.pack << "i" << g.n_items << "t" << g.n_tiles << "s" << g.passes;
+            key << "|l" << l << "c" << g.C << "d" << g.dtype << "G" << g.tc.G << "g" << g.tc.grid << "v"
+                << g.tc.variant << "k" << (g.tc.pack != 0) << "i" << g.n_items << "t" << g.n_tiles << "s" << g.passes;
         }
     }
     plan.key = key.str();
@@ -799,7 +822,6 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Ws &
         a.pcount = ws.pcount + (size_t)b0 * ws.frames;
         a.pcount_clear = ws.pcount + (size_t)b2 * ws.frames;
         a.n_frames = ws.frames;
-        a.pack_min = g.tc.pack == 2 ? 0 : 4 * ctx->ncu;
     }
     TimedLaunch tl{};
     if (timed) {
@@ -836,7 +858,6 @@ int enqueue_pass(pilot_ctx *ctx, const Plan &plan, const DevPtrs &dp, const Ws &
         e.phs_next = ws.phs + (size_t)b1 * ws.hyps;
         e.ppose_next = ws.ppose + (size_t)b1 * ws.hyps;
         e.pcount_next = ws.pcount + (size_t)b1 * ws.frames;
-        e.pack_min = a.pack_min;
     }
     HIPCHK(ctx, launch_epilogue(e, s));
     ctx->launches[g.stat_class]++;
@@ -1596,34 +1617,40 @@ int serving_rebuild(pilot_ctx *ctx)
             slot_of.push_back(i);
         }
     for (int l = 0; l < PILOT_MAX_LEVELS; ++l) {
-        std::map<std::array<int, 6>, std::vector<int>> by_class;
+        // slots whose tiles share a kernel instantiation share a launch, each
+        // with its own anchors per lane group (set in its descriptor at
+        // admission); serving steps run their groups one after another
+        std::map<std::array<int, 4>, std::vector<int>> by_class;
+        std::vector<TileConfig> tck(frames.size());
         for (int k = 0; k < (int)frames.size(); ++k)
             if (l < frames[k].n_levels) {
                 const pilot_level &L = frames[k].level[l];
-                const TileConfig tc = serving_tile(ctx, L.C, L.dtype, L.N, frames[k].M, (long)L.H * L.W);
-                by_class[{L.C, L.dtype, tc.G, tc.PPG, tc.variant, tc.pack}].push_back(k);
+                tck[k] = serving_tile(ctx, L.C, L.dtype, L.N, frames[k].M, (long)L.H * L.W);
+                by_class[{L.C, L.dtype, tck[k].G, tck[k].variant}].push_back(k);
             }
         for (auto &kv : by_class) {
             LaunchGroup g{};
             g.level = l;
             g.C = kv.first[0];
             g.dtype = kv.first[1];
-            const pilot_level &L0 = frames[kv.second[0]].level[l];
-            g.tc = serving_tile(ctx, g.C, g.dtype, L0.N, frames[kv.second[0]].M, (long)L0.H * L0.W);
             g.item_off = (int)plan.items.size();
             g.tile_off = (int)plan.tiles.size();
+            int most = kv.second[0], most_items = -1;
             for (int k : kv.second) {
                 const int slot = slot_of[k];
-                const int nht = (frames[k].M + g.tc.G - 1) / g.tc.G;
-                const int npt = n_ptiles_of(g.tc, frames[k].level[l].N);
+                const TileConfig &t = tck[k];
+                const int nht = (frames[k].M + t.G - 1) / t.G;
+                const int npt = n_ptiles_of(t, frames[k].level[l].N);
+                if (nht * npt > most_items) most = k, most_items = nht * npt;
                 for (int ht = 0; ht < nht; ++ht) {
-                    const int h0 = ht * g.tc.G, nh = std::min(g.tc.G, frames[k].M - h0);
+                    const int h0 = ht * t.G, nh = std::min(t.G, frames[k].M - h0);
                     plan.tiles.push_back(TileItem{slot, ht, (int)plan.items.size() - g.item_off, npt,
                                                   ctx->slots[slot].hyp_base + h0, nh});
                     for (int pt = 0; pt < npt; ++pt)
                         plan.items.push_back(WorkItem{slot, ctx->slots[slot].hyp_base + h0, pt, nh});
                 }
             }
+            g.tc = tck[most];
             g.n_items = (int)plan.items.size() - g.item_off;
             g.n_tiles = (int)plan.tiles.size() - g.tile_off;
             g.passes = 1;
@@ -1701,6 +1728,8 @@ int pilot_admit(pilot_ctx *ctx, const pilot_frame *frame, const pilot_result *re
     for (int l = 0; l < frame->n_levels; ++l) {
         const pilot_level &L = frame->level[l];
         const TileConfig tc = serving_tile(ctx, L.C, L.dtype, L.N, frame->M, (long)L.H * L.W);
+        d.lv[l].ppg = tc.PPG;
+        d.lv[l].pack_min = INT_MAX;          // serving walks contiguous tiles
         if (uses_gram(tc)) {
             gneed[l] = true;
             gfmt[l] = gram_format(tc, L.dtype);
