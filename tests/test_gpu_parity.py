@@ -303,6 +303,38 @@ def test_packed_hypothesis_tiles_leave_results_bitwise_unchanged(tmp_path, dtype
             assert a["best"] == b["best"], (pack, i)
 
 
+@pytest.mark.parametrize("dtype,variant", [("f32", 1), ("f32", 2), ("f32", 3), ("bf16", 9), ("bf16", 10)])
+def test_frames_with_different_tiles_share_a_launch(tmp_path, dtype, variant):
+    """Two frames whose tuned tiles share the kernel instantiation (same G and
+    variant) but not the anchors per lane group nor the packing rule run in
+    one launch per pass, each walked with its own tile (read from its level
+    descriptor): solved together they give bitwise what each gives alone."""
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    d = 0 if dtype == "f32" else 1
+    fr = [pyramid_frame(seed=31, N=900, M=37, iters=(5, 5, 5)), pyramid_frame(seed=32, N=700, M=13, iters=(4, 6, 3))]
+    if dtype == "bf16":
+        fr = [bf16_copy(f) for f in fr]
+    cache = tmp_path / "tune.txt"
+    with open(cache, "w") as fh:
+        for f, (ppg, pack) in zip(fr, ((2, 0), (8, 2))):
+            for L in f.levels:
+                fh.write(f"C{L.C}_d{d}_N{_floor_log2(L.N)}_M{_floor_log2(f.M)}_P{_floor_log2(L.H * L.W)}_v3 "
+                         f"4 {ppg} 0 {variant} {pack if variant >= 3 else 0}\n")
+    c = Context(0, tune_cache=str(cache))
+    dfs = [DeviceFrame(f, dtype=dtype) for f in fr]
+    L0, L1 = fr[0].levels[0], fr[1].levels[0]
+    assert "PPG=2" in c.tile_choice(L0.C, d, L0.N, fr[0].M, L0.H * L0.W)
+    assert "PPG=8" in c.tile_choice(L1.C, d, L1.N, fr[1].M, L1.H * L1.W)
+    say(f"mixed tiles in one launch: dtype={dtype} variant={variant}")
+    alone = [c.solve([x])[0].numpy() for x in dfs]
+    both = [r.numpy() for r in c.solve(dfs)]
+    torch.cuda.synchronize()
+    for i in range(2):
+        for k in ("poses", "cost", "iterations", "status"):
+            assert np.array_equal(alone[i][k], both[i][k]), (i, k)
+        assert alone[i]["best"] == both[i]["best"], i
+
+
 @pytest.mark.parametrize("scale", [1e-9, 1e-6, 1e-3, 1.0, 1e3, 1e6, 1e9])
 def test_cauchy_loss_per_pair_matches_oracle(ctx, scale):
     """The Cauchy loss of a pair (its log(1 + q) comes from a short atanh
