@@ -758,11 +758,13 @@ hipError_t launch_pack(const FrameDev *frames, int n_frames, int max_M, const in
 // order, P at a time per work item, so the locality of their gathers (taps of
 // neighbouring anchors under one pose fall in neighbouring cells, sharing
 // cache lines in L1 and L2) depends on how the caller listed the anchors.
-// The library therefore sorts each level's anchors by the Morton code of
-// their ground position (x, y quantised to 64 x 64 cells over the level's
-// bounding box) before the first pass and walks its own copies.  The sums
-// over anchors change only in their rounding order; the order is a function
-// of the anchor set alone (ties of one cell keep the caller's order).
+// The library therefore sorts a level's anchors (the runtime decides which
+// levels: enough anchor x hypothesis pairs per pass to repay the sort) by the
+// Morton code of their ground position (x, y quantised to 256 x 256 cells
+// over the level's bounding box) before the first pass and walks its own
+// copies.  The sums over anchors change only in their rounding order; the
+// order is a function of the anchor set alone (ties of one cell keep the
+// caller's order).
 
 namespace {
 constexpr int kSortThreads = 1024;
