@@ -70,6 +70,29 @@ def test_static_solve_equals_solve_on_two_calls(tmp_path):
     ref.close()
 
 
+def test_static_solve_at_the_benchmark_size():
+    """The benchmark's workload (1 frame, N = 16384, M = 1024, bf16 pyramid
+    up to 480x640x128, the committed tile database, anchors sorted, packed
+    tiles) fits the fixed scratch and solves bitwise as pilot_solve does."""
+    import os
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    tiles = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2606_31098_amd",
+                         "tiles_gfx950.txt")
+    f = S.make_frame(3, 0)
+    d = DeviceFrame(f, dtype="bf16")
+    ref = Context(0, tune_cache=tiles)
+    r = ref.solve([d])[0]
+    torch.cuda.synchronize()
+    r = r.numpy()
+    ctx = Context(0, tune_cache=tiles, hbm_budget_bytes=4096)
+    say("pilot_solve_static: the 16384 x 1024 bf16 frame")
+    s = ctx.solve_static([d])[0]
+    torch.cuda.synchronize()
+    assert _same(s.numpy(), r), "static solve differs from pilot_solve at the benchmark size"
+    ctx.close()
+    ref.close()
+
+
 def test_static_solve_refuses_frames_beyond_the_scratch():
     from paper_2606_31098_amd.pilot import Context, DeviceFrame, DeviceResult, PilotError
     # 65536 hypotheses over 8192 anchors: about 110 MB of LM states and
