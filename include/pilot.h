@@ -231,7 +231,11 @@ const char *pilot_last_error(const pilot_ctx *ctx);
 /* Refine frames[0..n_frames) (each with its own hypotheses) coarse to fine
  * and select the best hypothesis of each frame (multi-hypothesis LM of the
  * Method's "Multi-Sensor Optimization").  results[i] receives frame i.
- * Enqueued on the context stream; no host synchronisation inside. */
+ * Enqueued on the context stream; no host synchronisation inside.  When a
+ * pass has launches for frames of different tiles, they are forked through
+ * events onto three streams the context owns and joined back before the
+ * next pass, so the whole solve stays ordered after earlier and before
+ * later work on the context stream. */
 int pilot_solve(pilot_ctx *ctx, const pilot_frame *frames, int n_frames,
                 const pilot_result *results);
 
