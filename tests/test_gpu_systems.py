@@ -241,6 +241,34 @@ def test_anchor_order_does_not_change_results(alone):
         assert not fails, fails
 
 
+def test_hypothesis_order_does_not_change_results(alone, tmp_path):
+    """A hypothesis' sums do not depend on its tile, slot or the hypotheses
+    beside it, so listing a frame's hypotheses in another order permutes its
+    results and nothing else (bitwise), with contiguous tiles (the built-in
+    heuristic) and with packed tiles (a tile file with pack mode 2)."""
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    fr, dfs, ref = alone
+    f = fr[2]
+    g = copy.deepcopy(f)
+    order = np.random.default_rng(8).permutation(f.M)
+    g.poses = np.ascontiguousarray(f.poses[order])
+    packed = tmp_path / "tiles_packed.txt"
+    with open(packed, "w") as fh:
+        for L in f.levels:
+            fh.write(f"C{L.C}_d0_N{L.N.bit_length() - 1}_M{f.M.bit_length() - 1}_P{(L.H * L.W).bit_length() - 1}_v3 "
+                     "4 2 0 3 2\n")
+    for tiles in (None, str(packed)):
+        say(f"hypotheses permuted, tiles {tiles}")
+        ctx = Context(0, tune_cache=tiles)
+        a = as_np(ctx.solve([DeviceFrame(f)])[0])
+        b = as_np(ctx.solve([DeviceFrame(g)])[0])
+        torch.cuda.synchronize()
+        for k in ("poses", "cost", "iterations", "status"):
+            assert np.array_equal(b[k], a[k][order]), (tiles, k)
+        assert b["cost"][b["best"]] == a["cost"][a["best"]], tiles
+        ctx.close()
+
+
 def test_default_sorts_only_large_levels():
     """By default a level is sorted when it has at least 2^23 anchor x
     hypothesis pairs per pass: a frame of 8192 anchors and 1024 hypotheses
