@@ -1,12 +1,10 @@
 """Shared helpers of the GPU parity tests (frames, rounding, comparisons)."""
 import copy
-import math
 import sys
 
 import numpy as np
 import torch
 
-import oracle
 from synth import frames as S
 
 POSE_TOL_M = 1e-3          # FP32 path: final pose within 1 mm ...

@@ -9,7 +9,7 @@ import torch
 
 import oracle
 from synth import frames as S
-from tests.gpu_common import BF16_TOL_DEG, BF16_TOL_M, POSE_TOL_DEG, POSE_TOL_M, bf16_copy, say
+from tests.gpu_common import BF16_TOL_DEG, BF16_TOL_M, POSE_TOL_DEG, POSE_TOL_M, say
 
 pytestmark = pytest.mark.gpu
 

@@ -1,7 +1,6 @@
 """GPU path (libpilot, through the C ABI) against the FP64 oracle, element by
 element on the same seeded inputs."""
 import copy
-import math
 
 import numpy as np
 import pytest

@@ -1,6 +1,5 @@
 """Batching, graph replay, serving and ABI error behaviour of libpilot on the GPU."""
 import copy
-import ctypes as C
 import math
 
 import numpy as np

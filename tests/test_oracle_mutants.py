@@ -6,7 +6,6 @@ runs the pin suite against that build in a subprocess; the suite must fail."""
 import os
 import subprocess
 import sys
-import tempfile
 
 import pytest
 

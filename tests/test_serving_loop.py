@@ -5,8 +5,6 @@ eligibility of a stream's next frame only after its previous one finished
 different streams overlap."""
 import itertools
 
-import pytest
-
 from paper_2606_31098_amd.serving import Request, ServingLoop
 
 
