@@ -70,6 +70,33 @@ def test_static_solve_equals_solve_on_two_calls(tmp_path):
     ref.close()
 
 
+def test_static_solve_of_a_batch_with_concurrent_launches(tmp_path):
+    """Three frames whose tiles use different pass-kernel variants form three
+    launch classes per pass, which run forked onto the context's side
+    streams: the static solve of the batch equals pilot_solve's bit for bit."""
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    fr = [_frame(51, N=900, M=21), _frame(52, N=500, M=9), _frame(53, N=700, M=40)]
+
+    def lb(n):
+        return max(int(n), 1).bit_length() - 1
+    path = tmp_path / "tiles_batch.txt"
+    with open(path, "w") as fh:
+        for f, (variant, G) in zip(fr, ((3, 4), (4, 8), (1, 4))):
+            for (H, W, C), L in zip(LEVELS, f.levels):
+                fh.write(f"C{C}_d0_N{lb(L.N)}_M{lb(f.M)}_P{lb(H * W)}_v3 {G} 2 0 {variant}\n")
+    dfs = [DeviceFrame(f) for f in fr]
+    ref = Context(0, tune_cache=str(path))
+    r = [x.numpy() for x in ref.solve(dfs)]
+    ctx = Context(0, tune_cache=str(path), hbm_budget_bytes=4096)
+    say("pilot_solve_static: a batch of three frames in three launch classes")
+    s = [x.numpy() for x in ctx.solve_static(dfs)]
+    torch.cuda.synchronize()
+    for i in range(3):
+        assert _same(s[i], r[i]), i
+    ctx.close()
+    ref.close()
+
+
 def test_static_solve_at_the_benchmark_size():
     """The benchmark's workload (1 frame, N = 16384, M = 1024, bf16 pyramid
     up to 480x640x128, the committed tile database, anchors sorted, packed
