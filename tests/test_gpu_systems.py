@@ -290,6 +290,25 @@ def test_default_sorts_only_large_levels():
     assert not fails, fails
 
 
+def test_sort_keeps_the_caller_order_of_anchors_in_one_cell():
+    """Degenerate ground positions: every anchor at the same (x, y) (a
+    vertical column of points) gives a zero-size bounding box, every anchor
+    the same sort cell, and so the caller's order: the sorted solve equals
+    the caller-order solve bit for bit."""
+    from paper_2606_31098_amd import _abi as A
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    f = small(34, N=300, M=5, iters=(3, 3, 3))
+    for L in f.levels:
+        L.x = np.full_like(L.x, L.x[0])
+        L.y = np.full_like(L.y, L.y[0])
+    d = DeviceFrame(f)
+    say("anchors in one sort cell")
+    a = as_np(Context(0, flags=A.FLAG_SORT_ANCHORS).solve([d])[0])
+    b = as_np(Context(0, flags=A.FLAG_KEEP_ORDER).solve([d])[0])
+    torch.cuda.synchronize()
+    assert same(a, b)
+
+
 def test_levels_above_the_sort_limit_keep_the_caller_order():
     """Levels of more than 16384 anchors are walked in the caller's order even
     under PILOT_FLAG_SORT_ANCHORS: that context and one with
