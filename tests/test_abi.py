@@ -56,7 +56,10 @@ def test_binding_constants_match_header():
     from paper_2606_31098_amd import _abi as A
     src = open(HEADER).read()
     for name, val in [("PILOT_EINVAL", A.EINVAL), ("PILOT_ENOMEM", A.ENOMEM), ("PILOT_EDEVICE", A.EDEVICE),
-                      ("PILOT_EAGAIN", A.EAGAIN), ("PILOT_EUNSUPPORTED", A.EUNSUPPORTED)]:
+                      ("PILOT_EAGAIN", A.EAGAIN), ("PILOT_EUNSUPPORTED", A.EUNSUPPORTED),
+                      ("PILOT_FLAG_NO_GRAPH", A.FLAG_NO_GRAPH), ("PILOT_FLAG_AUTOTUNE", A.FLAG_AUTOTUNE),
+                      ("PILOT_FLAG_PROFILE", A.FLAG_PROFILE), ("PILOT_FLAG_KEEP_ORDER", A.FLAG_KEEP_ORDER),
+                      ("PILOT_FLAG_SORT_ANCHORS", A.FLAG_SORT_ANCHORS)]:
         m = re.search(name + r"\s*=\s*(-?\d+)", src)
         assert m and int(m.group(1)) == val, name
     for name, val in [("PILOT_MAX_LEVELS", A.MAX_LEVELS)]:
