@@ -104,6 +104,25 @@ def test_bf16_solve_matches_oracle_on_rounded_inputs(ctx):
     assert not fails, fails
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_solve_without_the_cost_tolerance_matches_oracle(ctx, dtype):
+    """The LM stops only on the step size and the iteration cap (no relative
+    cost tolerance): the pose parity does not rest on that stopping rule."""
+    f = pyramid_frame(seed=6)
+    f.lm["cost_tol"] = 0.0
+    say(f"solve pyramid seed=6 without the cost tolerance dtype={dtype}")
+    gpu = solve_gpu(ctx, f, dtype=dtype)
+    ref = bf16_copy(f) if dtype == "bf16" else f
+    orc = oracle.solve(ref, threads=8)
+    tol_m, tol_deg = (BF16_TOL_M, BF16_TOL_DEG) if dtype == "bf16" else (POSE_TOL_M, POSE_TOL_DEG)
+    rows, fails = compare_solutions(f, gpu, orc, tol_m, tol_deg, f"no-cost-tol-{dtype}")
+    for r in rows:
+        say(r)
+    assert not fails, fails
+    assert check_best(f, gpu, orc, tol_m, tol_deg)
+    assert np.all(gpu["iterations"] <= sum(L.iters for L in f.levels))
+
+
 def test_noise_free_frame_converges_to_ground_truth(ctx):
     f = S.make_frame(1, 0, noise=False)
     say("solve noise-free config-1 frame")
