@@ -5,7 +5,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpilot.so")
+# PILOT_LIB_OVERRIDE names another build of the same library (the host-sanitized
+# copy of build_host_sanitized); by default the in-tree libpilot.so
+LIB_PATH = os.environ.get("PILOT_LIB_OVERRIDE") or os.path.join(HERE, "libpilot.so")
 
 MAX_LEVELS = 4
 OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5

@@ -9,7 +9,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "pilot.h")
-LIB = os.path.join(ROOT, "paper_2606_31098_amd", "libpilot.so")
+# the in-tree library, or the build PILOT_LIB_OVERRIDE names (the host-sanitized copy)
+LIB = os.environ.get("PILOT_LIB_OVERRIDE") or os.path.join(ROOT, "paper_2606_31098_amd", "libpilot.so")
 
 
 def declared_functions():
