@@ -239,6 +239,31 @@ def test_tile_shapes_and_kernel_variants_match_oracle(tmp_path, variant, G, dtyp
     assert not fails, fails
 
 
+@pytest.mark.parametrize("G", [4, 8])
+def test_sums_in_lds_leave_solves_bitwise_unchanged(tmp_path, G):
+    """Variant 10 runs variant 9's per-pair arithmetic with the lane's running
+    sums kept in LDS between anchors instead of registers: the same FMAs in the
+    same order, so solves are bitwise the same (bf16 maps, packed tiles)."""
+    from paper_2606_31098_amd.pilot import Context, DeviceFrame
+    f = bf16_copy(pyramid_frame(seed=9, N=900, M=19, iters=(4, 4, 4)))
+    out = {}
+    for variant in (9, 10):
+        cache = tmp_path / f"tune{variant}.txt"
+        with open(cache, "w") as fh:
+            for L in f.levels:
+                fh.write(f"C{L.C}_d1_N{_floor_log2(L.N)}_M{_floor_log2(f.M)}_P{_floor_log2(L.H * L.W)}_v3 "
+                         f"{G} 2 0 {variant} 2\n")
+        c = Context(0, tune_cache=str(cache))
+        L0 = f.levels[0]
+        assert f"V={variant}" in c.tile_choice(L0.C, 1, L0.N, f.M, L0.H * L0.W)
+        say(f"variant={variant} G={G} bf16 solve")
+        out[variant] = c.solve([DeviceFrame(f, dtype="bf16")])[0].numpy()
+        c.close()
+    for k in ("poses", "cost", "iterations", "status"):
+        assert np.array_equal(out[9][k], out[10][k]), k
+    assert out[9]["best"] == out[10]["best"]
+
+
 @pytest.mark.parametrize("variant", [9, 10])
 @pytest.mark.parametrize("G", [1, 2])
 def test_narrow_lane_groups_match_oracle(tmp_path, variant, G):
